@@ -1,0 +1,148 @@
+/*
+ * convhull.h -- C ABI of the MI355X (gfx950) convex-hull library.
+ *
+ * The library computes, on the GPU, the heaphull-style filter and a device
+ * hull pass described by A. Keith, H. Ferrada, C. A. Navarro, "Accelerating
+ * the Convex Hull Computation with a Parallel GPU Algorithm" (arXiv 2209.12310):
+ *   - Alg. 1 (heaphull): n points P[1..n] in, the hull CH[1..h] out in
+ *     counter-clockwise order.
+ *   - Alg. 2 (GPUfilter) and Sec. III: the extreme points (four axis extremes,
+ *     then the four points closest in Manhattan distance to the corners of
+ *     their box) form an octagon; a point survives when it lies outside it.
+ *   - Sec. I, stage 1: a point on a side of the octagon that is not one of
+ *     its vertices is discarded.
+ *
+ * Conventions shared by every entry point:
+ *   - Points are interleaved float32 pairs (x0, y0, x1, y1, ...), at least
+ *     8-byte aligned. Every coordinate must equal k * 2^-20 for an integer k
+ *     in [0, 2^20) (the value -0.0 counts as 0). Anything else (NaN, inf,
+ *     outside [0,1), off the grid) is a domain error. On this grid every
+ *     orientation test is exact, so results are bit-for-bit reproducible.
+ *   - Indices are 0-based uint32 (the paper's arrays are 1-based).
+ *   - The hull lists the strict vertices (collinear boundary points are not
+ *     vertices) counter-clockwise, starting at the lexicographic minimum
+ *     (smallest x, then smallest y). Duplicated coordinates are reported by
+ *     their smallest index. A single distinct point gives h = 1; a collinear
+ *     set gives its two end points, lexicographic minimum first; n = 0 gives
+ *     h = 0.
+ *   - Pointers named d_* are device memory, h_* host memory. All buffers are
+ *     owned by the caller. The library allocates no device memory on any call
+ *     after ch_ctx_create; scratch memory is the caller's workspace d_ws of at
+ *     least the size the matching *_workspace_bytes function returns.
+ *   - A workspace passed to a context must not be written by the caller while
+ *     that context uses it; the library keeps its own counters there in a
+ *     consistent state from one call to the next.
+ *   - stream is a hipStream_t (NULL = the legacy default stream).
+ *   - A ch_ctx is used by one host thread at a time.
+ */
+#ifndef CONVHULL_H
+#define CONVHULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CH_OK = 0,
+  CH_E_INVALID_ARG = 1, /* bad pointer, size, alignment or workspace size   */
+  CH_E_DOMAIN = 2,      /* a coordinate is off the 2^-20 grid in [0,1)     */
+  CH_E_CAPACITY = 3,    /* output buffer too small; required size reported */
+  CH_E_NOMEM = 4,       /* host or device allocation failed (create only)  */
+  CH_E_DEVICE = 5,      /* a HIP runtime call failed                       */
+  CH_E_BUSY = 6,        /* admission refused: budget or queue full         */
+  CH_E_TIMEOUT = 7,     /* a wait ran out of time                          */
+  CH_E_CANCELLED = 8,   /* the request was cancelled                       */
+  CH_E_SHUTDOWN = 9,    /* the server stopped before the request finished  */
+  CH_E_NOT_FOUND = 10   /* unknown ticket                                  */
+} ch_status;
+
+/* Count value ch_filter writes when the input has a domain error. */
+#define CH_COUNT_DOMAIN_ERROR 0xFFFFFFFFu
+/* Largest point count of one set (indices and counts stay below 2^31). */
+#define CH_MAX_POINTS 0x7FFFFFFFu
+
+typedef struct ch_ctx ch_ctx;
+
+/* The octagon of Sec. III in slot order E, NE, N, NW, W, SW, S, SE:
+ * grid coordinates (kx = x * 2^20) and the smallest index holding each
+ * vertex. Ties in an extreme are broken towards the counter-clockwise end of
+ * the supporting side (E: larger y, N: smaller x, W: smaller y, S: larger x,
+ * NE/SE: larger y, NW/SW: smaller y). */
+typedef struct {
+  int32_t kx[8];
+  int32_t ky[8];
+  uint32_t idx[8];
+} ch_octagon;
+
+/* Create a context bound to HIP device `hip_device`. tune_cache_path may be
+ * NULL. Allocates pinned host staging memory and nothing on the device.
+ * Errors: CH_E_INVALID_ARG (out is NULL), CH_E_DEVICE, CH_E_NOMEM. */
+ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** out);
+/* Destroy a context (NULL is ignored). Waits for nothing: the caller must
+ * have synchronised the streams it used. */
+void ch_ctx_destroy(ch_ctx* ctx);
+/* Static text for a status code. */
+const char* ch_status_string(ch_status s);
+/* Detail text of the last error on this context (never NULL). */
+const char* ch_last_error(const ch_ctx* ctx);
+
+/* Device workspace bytes needed by ch_filter / ch_hull for n points. */
+size_t ch_filter_workspace_bytes(uint32_t n);
+size_t ch_hull_workspace_bytes(uint32_t n);
+
+/*
+ * ch_filter -- the filtering stage (Alg. 2 with Sec. III's extremes).
+ * Asynchronous: enqueues its kernels on `stream` and returns.
+ *   d_xy        n points (see conventions).
+ *   d_survivors capacity n; receives the surviving indices in ascending order.
+ *   d_count     one uint32: the number of survivors, or
+ *               CH_COUNT_DOMAIN_ERROR when the input has a domain error (the
+ *               other outputs are then unspecified).
+ *   d_label     optional (NULL to skip), n bytes: 0 for a discarded point, else
+ *               1 + floor(i/2) for the first octagon edge i (from slot i to
+ *               slot i+1) the point lies strictly outside of, or for a vertex
+ *               outside no edge 1 + floor(k/2) with k its first slot. (The
+ *               paper's findQueue rule is not given; this one is ours.)
+ *   d_oct       optional (NULL to skip): the octagon.
+ *   d_ws        workspace of ws_bytes >= ch_filter_workspace_bytes(n).
+ * Returns CH_OK once enqueued; CH_E_INVALID_ARG for NULL required pointers,
+ * n > CH_MAX_POINTS, a misaligned d_xy or a small workspace; CH_E_DEVICE when
+ * a launch fails. n = 0 writes a zero count.
+ */
+ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_survivors,
+                    uint32_t* d_count, uint8_t* d_label, ch_octagon* d_oct, void* d_ws,
+                    size_t ws_bytes, void* stream);
+
+/*
+ * ch_hull -- the whole path of Alg. 1: filter, then the hull of the survivors
+ * on the device. Synchronous with respect to `stream`: returns after the hull
+ * is in host memory.
+ *   h_hull_idx  host buffer of `cap` entries for the hull indices.
+ *   h_out       receives h.
+ * Errors: CH_E_DOMAIN (outputs untouched), CH_E_CAPACITY (*h_out = required
+ * h, h_hull_idx untouched), CH_E_INVALID_ARG, CH_E_DEVICE.
+ */
+ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_idx, uint32_t cap,
+                  uint32_t* h_out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around each
+ * kernel. While enabled, every ch_* call synchronises its stream before
+ * returning. ch_profile_read fills up to cap records and returns the number
+ * of kernels seen in *n_out. */
+typedef struct {
+  const char* name;   /* static string */
+  uint64_t launches;
+  double total_ms;
+} ch_kernel_stat;
+ch_status ch_profile_enable(ch_ctx* ctx, int on);
+ch_status ch_profile_reset(ch_ctx* ctx);
+ch_status ch_profile_read(ch_ctx* ctx, ch_kernel_stat* out, int cap, int* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONVHULL_H */

@@ -1,0 +1,190 @@
+"""MI355X-native convex hull: the heaphull-style octagon filter and a device
+hull pass (Keith, Ferrada, Navarro, arXiv 2209.12310), as HIP kernels for
+gfx950 behind the C ABI in include/convhull.h.
+
+This package is a thin binding: it checks tensor arguments, allocates device
+buffers with torch, and passes pointers and the current HIP stream to the
+library. It never computes any part of the hull itself.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _capi
+from ._capi import CH_COUNT_DOMAIN_ERROR, KernelStat, Octagon, load
+
+__all__ = ["Context", "ConvexHullError", "DomainError", "CapacityError", "FilterResult",
+           "default_context", "filter", "hull", "load"]
+
+
+class ConvexHullError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_capi.STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+
+
+class DomainError(ConvexHullError, ValueError):
+    pass
+
+
+class CapacityError(ConvexHullError):
+    pass
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_points(xy):
+    torch = _torch()
+    if not isinstance(xy, torch.Tensor) or not xy.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if xy.dtype != torch.float32 or xy.dim() != 2 or xy.shape[1] != 2:
+        raise TypeError("points must be float32 of shape (n, 2)")
+    if not xy.is_contiguous():
+        raise ValueError("points must be contiguous (interleaved x, y)")
+    n = xy.shape[0]
+    if n > _capi.CH_MAX_POINTS:
+        raise ValueError("too many points")
+    return n
+
+
+@dataclass
+class FilterResult:
+    survivors: "object"      # torch uint32-valued int64 tensor on the device, ascending
+    count: int
+    labels: "object | None"  # torch uint8 tensor (n,) or None
+    octagon: "dict | None"   # {'kx','ky','idx'} numpy arrays in slot order E..SE
+
+
+class Context:
+    """A library context bound to one HIP device, with a cached workspace."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self._lib.ch_ctx_create(device, None, ctypes.byref(h))
+        if st != _capi.CH_OK:
+            raise ConvexHullError(st, "ch_ctx_create failed")
+        self._h = h
+        self._ws = None
+
+    # -- plumbing ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ch_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st: int):
+        detail = self._lib.ch_last_error(self._h).decode(errors="replace")
+        if st == _capi.CH_E_DOMAIN:
+            raise DomainError(st, detail)
+        if st == _capi.CH_E_CAPACITY:
+            raise CapacityError(st, detail)
+        raise ConvexHullError(st, detail)
+
+    def workspace(self, nbytes: int):
+        """A device byte buffer of at least nbytes (reused across calls)."""
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def stream_handle(self):
+        torch = _torch()
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- entry points -----------------------------------------------------
+    def filter_async(self, xy, survivors, count, labels=None, octagon_dev=None):
+        """ch_filter on caller-provided device buffers (uint32 views as int32
+        tensors); enqueues on the current stream and returns immediately."""
+        n = _check_points(xy)
+        ws_bytes = self._lib.ch_filter_workspace_bytes(n)
+        ws = self.workspace(ws_bytes)
+        st = self._lib.ch_filter(
+            self._h, ctypes.c_void_p(xy.data_ptr()), n, ctypes.c_void_p(survivors.data_ptr()),
+            ctypes.c_void_p(count.data_ptr()),
+            ctypes.c_void_p(labels.data_ptr()) if labels is not None else None,
+            ctypes.c_void_p(octagon_dev.data_ptr()) if octagon_dev is not None else None,
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+
+    def filter(self, xy, labels: bool = False, octagon: bool = False) -> FilterResult:
+        torch = _torch()
+        n = _check_points(xy)
+        dev = xy.device
+        surv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=dev)
+        lab = torch.empty(max(n, 1), dtype=torch.uint8, device=dev) if labels else None
+        octd = torch.empty(24, dtype=torch.int32, device=dev) if octagon else None
+        self.filter_async(xy, surv, cnt, lab, octd)
+        c = int(cnt.cpu().numpy().view(np.uint32)[0])
+        if c == CH_COUNT_DOMAIN_ERROR:
+            raise DomainError(_capi.CH_E_DOMAIN, "input outside the 2^-20 grid on [0,1)")
+        oct_np = None
+        if octagon and n:
+            o = octd.cpu().numpy()
+            oct_np = {"kx": o[0:8].copy(), "ky": o[8:16].copy(), "idx": o[16:24].view(np.uint32).copy()}
+        return FilterResult(survivors=surv[:c], count=c, labels=lab[:n] if labels else None,
+                            octagon=oct_np)
+
+    def hull(self, xy, cap: int | None = None) -> np.ndarray:
+        """Counter-clockwise hull vertex indices (uint32 numpy array)."""
+        n = _check_points(xy)
+        ws_bytes = self._lib.ch_hull_workspace_bytes(n)
+        ws = self.workspace(ws_bytes)
+        if cap is None:
+            cap = max(min(n, 1 << 21), 1)
+        out = np.empty(cap, np.uint32)
+        h = ctypes.c_uint32(0)
+        st = self._lib.ch_hull(self._h, ctypes.c_void_p(xy.data_ptr()), n,
+                               out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(h),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+        return out[: h.value].copy()
+
+    # -- profiling --------------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._lib.ch_profile_enable(self._h, 1 if on else 0)
+
+    def profile_reset(self):
+        self._lib.ch_profile_reset(self._h)
+
+    def profile_read(self) -> dict:
+        arr = (KernelStat * 64)()
+        n = ctypes.c_int(0)
+        self._lib.ch_profile_read(self._h, ctypes.cast(arr, ctypes.c_void_p), 64, ctypes.byref(n))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+                for i in range(min(n.value, 64))}
+
+
+_default = None
+
+
+def default_context() -> Context:
+    global _default
+    if _default is None:
+        _default = Context(0)
+    return _default
+
+
+def filter(xy, labels: bool = False, octagon: bool = False) -> FilterResult:  # noqa: A001
+    return default_context().filter(xy, labels=labels, octagon=octagon)
+
+
+def hull(xy, cap: int | None = None) -> np.ndarray:
+    return default_context().hull(xy, cap)

@@ -1,0 +1,447 @@
+// Host side of the C ABI declared in include/convhull.h: argument checks,
+// workspace layout, kernel sequencing, result staging and profiling.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/convhull.h"
+#include "ch_internal.hpp"
+
+namespace chk {
+hipError_t launch_ws_init(void* ws, hipStream_t st);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);
+uint32_t reduce_blocks(uint32_t n);
+hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, Header* hdr, Result* res,
+                          double* partials, uint64_t* tstat, uint32_t ntiles2, uint32_t blocks,
+                          hipStream_t st);
+hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
+                         uint32_t ntiles, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
+                         hipStream_t st);
+hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
+hipError_t launch_hull_round(int mode, uint32_t grid, const float* xy, const uint32_t* in_idx,
+                             const Rec* in_rec, const uint32_t* in_count, Rec* out_rec,
+                             uint32_t* out_count, uint32_t* tile_ctr, Result* res,
+                             uint32_t* res_idx, const Octagon* oct, hipStream_t st);
+hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t max_in,
+                            uint64_t* bot, uint64_t* top, uint32_t* cnt, Rec* lst_lo, Rec* lst_up,
+                            const Octagon* oct, Result* res, hipStream_t st);
+hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl, uint32_t cu,
+                               uint32_t shift, Rec* tmp_lo, Rec* tmp_up, uint32_t* wcnt_lo,
+                               uint32_t* wcnt_up, Rec* dst_lo, Rec* dst_up, Result* res,
+                               hipStream_t st);
+hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
+                              Result* res, uint32_t* res_idx, hipStream_t st);
+}  // namespace chk
+
+using namespace chk;
+
+namespace {
+
+constexpr uint32_t kPinIdx = 2048;  // hull indices fetched with the result block
+constexpr int kWinShift = 4096 / 2;
+
+struct KStat {
+  const char* name;
+  uint64_t launches;
+  double ms;
+};
+
+}  // namespace
+
+struct ch_ctx {
+  int device = 0;
+  int cu_count = 0;
+  unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
+  std::string err;
+  bool prof = false;
+  std::vector<KStat> stats;
+  struct Pending { int stat; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+ch_status fail(ch_ctx* ctx, ch_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+ch_status fail(ch_ctx* ctx, ch_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+ch_status hip_fail(ch_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, CH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int stat_index(ch_ctx* ctx, const char* name) {
+  for (size_t i = 0; i < ctx->stats.size(); ++i)
+    if (std::strcmp(ctx->stats[i].name, name) == 0) return (int)i;
+  ctx->stats.push_back({name, 0, 0.0});
+  return (int)ctx->stats.size() - 1;
+}
+
+hipEvent_t take_event(ch_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  ch_ctx* ctx;
+  hipStream_t st;
+  int stat = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(ch_ctx* c, hipStream_t s, const char* name) : ctx(c), st(s) {
+    if (!ctx->prof) return;
+    stat = stat_index(ctx, name);
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!ctx->prof || !a || !b) return;
+    (void)hipEventRecord(b, st);
+    ctx->pending.push_back({stat, a, b});
+  }
+};
+
+void prof_collect(ch_ctx* ctx, hipStream_t st) {
+  if (!ctx->prof || ctx->pending.empty()) return;
+  (void)hipStreamSynchronize(st);
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->stats[p.stat].launches += 1;
+      ctx->stats[p.stat].ms += ms;
+    }
+    ctx->pool.push_back(p.a);
+    ctx->pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<unsigned char*>(ws) + off);
+}
+
+// Enqueues ws_init, pass 1 and pass 2. surv / count_out receive the survivors.
+ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
+                     uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
+                     hipStream_t st) {
+  const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
+  const uint32_t ntiles = filter_tiles(n);
+  Header* hdr = at<Header>(ws, L.hdr);
+  Result* res = at<Result>(ws, L.res);
+  hipError_t e;
+  {
+    ProfScope p(ctx, st, "ws_init");
+    e = launch_ws_init(ws, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "ws_init launch");
+  {
+    ProfScope p(ctx, st, "reduce8");
+    e = launch_reduce8(d_xy, n, head, hdr, res, at<double>(ws, L.partials), at<uint64_t>(ws, L.tstat),
+                       ntiles, reduce_blocks(n), st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
+  {
+    ProfScope p(ctx, st, "filter_compact");
+    e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), ntiles, surv, count_out, labels,
+                      st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "filter launch");
+  return CH_OK;
+}
+
+ch_status check_points(ch_ctx* ctx, const float* d_xy, uint32_t n) {
+  if (n > CH_MAX_POINTS) return fail(ctx, CH_E_INVALID_ARG, "n = %u exceeds CH_MAX_POINTS", n);
+  if (n && !d_xy) return fail(ctx, CH_E_INVALID_ARG, "d_xy is NULL");
+  if (reinterpret_cast<uintptr_t>(d_xy) & 7u)
+    return fail(ctx, CH_E_INVALID_ARG, "d_xy must be 8-byte aligned");
+  return CH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ch_status_string(ch_status s) {
+  switch (s) {
+    case CH_OK: return "ok";
+    case CH_E_INVALID_ARG: return "invalid argument";
+    case CH_E_DOMAIN: return "coordinate outside the 2^-20 grid on [0,1)";
+    case CH_E_CAPACITY: return "output capacity too small";
+    case CH_E_NOMEM: return "out of memory";
+    case CH_E_DEVICE: return "HIP runtime error";
+    case CH_E_BUSY: return "busy";
+    case CH_E_TIMEOUT: return "timed out";
+    case CH_E_CANCELLED: return "cancelled";
+    case CH_E_SHUTDOWN: return "shut down";
+    case CH_E_NOT_FOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** out) {
+  (void)tune_cache_path;
+  if (!out) return CH_E_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return CH_E_DEVICE;
+  DeviceGuard g(hip_device);
+  if (!g.ok) return CH_E_DEVICE;
+  ch_ctx* ctx = new (std::nothrow) ch_ctx();
+  if (!ctx) return CH_E_NOMEM;
+  ctx->device = hip_device;
+  if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) !=
+      hipSuccess)
+    ctx->cu_count = 256;
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kResBytes + 4 * kPinIdx,
+                    hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return CH_E_NOMEM;
+  }
+  *out = ctx;
+  return CH_OK;
+}
+
+void ch_ctx_destroy(ch_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* ch_last_error(const ch_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+size_t ch_filter_workspace_bytes(uint32_t n) { return layout(n).filter_end; }
+size_t ch_hull_workspace_bytes(uint32_t n) { return layout(n).total; }
+
+ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_survivors,
+                    uint32_t* d_count, uint8_t* d_label, ch_octagon* d_oct, void* d_ws,
+                    size_t ws_bytes, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (ch_status s = check_points(ctx, d_xy, n)) return s;
+  if (!d_count) return fail(ctx, CH_E_INVALID_ARG, "d_count is NULL");
+  if (n && !d_survivors) return fail(ctx, CH_E_INVALID_ARG, "d_survivors is NULL");
+  const Layout L = layout(n);
+  if (!d_ws || ws_bytes < L.filter_end)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", L.filter_end, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    hipError_t e = launch_set_u32(d_count, 0u, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set count");
+    return CH_OK;
+  }
+  if (ch_status s = run_filter(ctx, d_xy, n, d_survivors, d_count, d_label, d_ws, L, st)) return s;
+  if (d_oct) {
+    ProfScope p(ctx, st, "oct_out");
+    hipError_t e = launch_oct_out(at<Header>(d_ws, L.hdr), d_oct, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "oct_out launch");
+  }
+  prof_collect(ctx, st);
+  return CH_OK;
+}
+
+ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_idx, uint32_t cap,
+                  uint32_t* h_out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (ch_status s = check_points(ctx, d_xy, n)) return s;
+  if (!h_out) return fail(ctx, CH_E_INVALID_ARG, "h_out is NULL");
+  if (cap && !h_hull_idx) return fail(ctx, CH_E_INVALID_ARG, "h_hull_idx is NULL");
+  const Layout L = layout(n);
+  if (n && (!d_ws || ws_bytes < L.total))
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (n == 0) {
+    *h_out = 0;
+    return CH_OK;
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Header* hdr = at<Header>(d_ws, L.hdr);
+  Result* res = at<Result>(d_ws, L.res);
+  uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
+  uint32_t* surv = at<uint32_t>(d_ws, L.surv);
+  Rec* rec[2] = {at<Rec>(d_ws, L.recA), at<Rec>(d_ws, L.recB)};
+  if (ch_status s = run_filter(ctx, d_xy, n, surv, &hdr->count, nullptr, d_ws, L, st)) return s;
+
+  const Result* hres = reinterpret_cast<const Result*>(ctx->pinned);
+  const uint32_t* hidx = reinterpret_cast<const uint32_t*>(ctx->pinned + kResBytes);
+  const uint32_t pin_n = hull_cap(n) < kPinIdx ? hull_cap(n) : kPinIdx;
+  auto fetch = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(ctx->pinned, res, kResBytes + 4 * size_t(pin_n),
+                                  hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  };
+
+  int round = 0;
+  uint32_t grid = (n + kHullTile - 1) / kHullTile;
+  if (grid > (uint32_t)kHullGridMax) grid = kHullGridMax;
+  bool large = false;
+  int last_list = -1;  // record list holding the latest round's output
+  while (true) {
+    hipError_t e;
+    {
+      ProfScope p(ctx, st, round == 0 ? "hull_round0" : "hull_round");
+      e = launch_hull_round(round == 0 ? 0 : 1, grid, d_xy, surv, round ? rec[(round - 1) & 1] : nullptr,
+                            round == 0 ? &hdr->count : &res->round_cnt[round], rec[round & 1],
+                            &res->round_cnt[round + 1], &res->round_tile[round], res, res_idx,
+                            &hdr->oct, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hull round launch");
+    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull round");
+    prof_collect(ctx, st);
+    if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
+    if (hres->status == RES_DONE) break;
+    if (hres->status != RES_MORE) return fail(ctx, CH_E_DEVICE, "hull round status %u", hres->status);
+    // A round that keeps more than half of its input hands over to the
+    // large-hull path.
+    const uint32_t cin = hres->cin;
+    const uint32_t cout = hres->round_cnt[round + 1];
+    last_list = round & 1;
+    ++round;
+    if (uint64_t(cout) * 2 > cin || round + 1 >= kMaxRounds) {
+      large = true;
+      break;
+    }
+    grid = (cout + kHullTile - 1) / kHullTile;
+    if (grid > (uint32_t)kHullGridMax) grid = kHullGridMax;
+    if (grid < 1) grid = 1;
+  }
+
+  if (large) {
+    const uint32_t cin = hres->round_cnt[round];  // output of the last round
+    Rec* lstA = at<Rec>(d_ws, L.lstA);
+    Rec* lstB = at<Rec>(d_ws, L.lstB);
+    const size_t chain_cap = size_t(kColumns) + 2;
+    Rec* Alo = lstA; Rec* Aup = lstA + chain_cap;
+    Rec* Blo = lstB; Rec* Bup = lstB + chain_cap;
+    uint32_t* wcnt = at<uint32_t>(d_ws, L.wcnt);
+    const size_t wstride = chain_cap / 4096 + 4;
+    hipError_t e;
+    {
+      ProfScope p(ctx, st, "col_build");
+      e = launch_col_build(rec[last_list], &res->round_cnt[round], cin, at<uint64_t>(d_ws, L.colbot),
+                           at<uint64_t>(d_ws, L.coltop), at<uint32_t>(d_ws, L.colcnt), Alo, Aup,
+                           &hdr->oct, res, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "column build launch");
+    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "column build");
+    prof_collect(ctx, st);
+    uint32_t cl = hres->lcount, cu = hres->ucount;
+    int stall = 0, parity = 0;
+    for (uint64_t it = 0;; ++it) {
+      if (it > (uint64_t)4 * (cl + cu) + 8) return fail(ctx, CH_E_DEVICE, "window rounds did not settle");
+      if (cl <= 4096 && cu <= 4096) {
+        ProfScope p(ctx, st, "large_final");
+        e = launch_large_final(Alo, Aup, cl, cu, 1, res, res_idx, st);
+        break;
+      }
+      {
+        ProfScope p(ctx, st, "window_round");
+        e = launch_window_round(Alo, Aup, cl, cu, parity ? kWinShift : 0, Blo, Bup, wcnt,
+                                wcnt + wstride, Alo, Aup, res, st);
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "window round launch");
+      if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "window round");
+      prof_collect(ctx, st);
+      const uint32_t nl = hres->lcount, nu = hres->ucount;
+      stall = (nl == cl && nu == cu) ? stall + 1 : 0;
+      cl = nl;
+      cu = nu;
+      if (stall >= 2) {
+        ProfScope p(ctx, st, "large_final");
+        e = launch_large_final(Alo, Aup, cl, cu, 0, res, res_idx, st);
+        break;
+      }
+      parity ^= 1;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "large final launch");
+    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "large final");
+    prof_collect(ctx, st);
+    if (hres->status != RES_DONE) return fail(ctx, CH_E_DEVICE, "large hull status %u", hres->status);
+  }
+
+  const uint32_t h = hres->h;
+  *h_out = h;
+  if (h > cap) return fail(ctx, CH_E_CAPACITY, "hull has %u vertices, capacity %u", h, cap);
+  if (h <= pin_n) {
+    std::memcpy(h_hull_idx, hidx, size_t(h) * 4);
+  } else {
+    hipError_t e = hipMemcpyAsync(h_hull_idx, res_idx, size_t(h) * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hull copy");
+  }
+  return CH_OK;
+}
+
+ch_status ch_profile_enable(ch_ctx* ctx, int on) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  ctx->prof = on != 0;
+  return CH_OK;
+}
+
+ch_status ch_profile_reset(ch_ctx* ctx) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  for (auto& s : ctx->stats) { s.launches = 0; s.ms = 0.0; }
+  return CH_OK;
+}
+
+ch_status ch_profile_read(ch_ctx* ctx, ch_kernel_stat* out, int cap, int* n_out) {
+  if (!ctx || !n_out || (cap > 0 && !out)) return CH_E_INVALID_ARG;
+  const int n = (int)ctx->stats.size();
+  for (int i = 0; i < n && i < cap; ++i) {
+    out[i].name = ctx->stats[i].name;
+    out[i].launches = ctx->stats[i].launches;
+    out[i].total_ms = ctx->stats[i].ms;
+  }
+  *n_out = n;
+  return CH_OK;
+}
+
+}  // extern "C"
