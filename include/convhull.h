@@ -128,6 +128,38 @@ ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_surv
 ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_idx, uint32_t cap,
                   uint32_t* h_out, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Count values ch_hull_batch writes for a set it could not finish:
+ * CH_COUNT_DOMAIN_ERROR (above) for a domain error in that set;
+ * CH_COUNT_OVERFLOW when the set's candidates did not shrink to one workgroup
+ * within the batch's tile-hull rounds (only possible with thousands of points
+ * in convex position; ch_hull handles any set);
+ * CH_COUNT_INVALID for every set when the offsets are not non-decreasing from
+ * 0 to total_points. */
+#define CH_COUNT_OVERFLOW 0xFFFFFFFEu
+#define CH_COUNT_INVALID 0xFFFFFFFDu
+
+/* Device workspace bytes needed by ch_hull_batch. */
+size_t ch_hull_batch_workspace_bytes(uint32_t nsets, uint64_t total_points);
+
+/*
+ * ch_hull_batch -- Alg. 1 for many independent point sets at once.
+ * Asynchronous: enqueues a fixed sequence of kernels on `stream` (no host
+ * synchronisation, so the call can be captured in a HIP graph) and returns.
+ *   d_xy          all points, set after set, 16-byte aligned.
+ *   d_off         nsets + 1 uint64 offsets: set s is points [d_off[s],
+ *                 d_off[s+1]); d_off[0] = 0, d_off[nsets] = total_points.
+ *   total_points  below 2^32.
+ *   d_hull_idx    capacity total_points: the hull of set s, as indices local
+ *                 to the set (0 = its first point), starts at d_hull_idx[d_off[s]].
+ *   d_hull_count  nsets uint32: h of each set, or a CH_COUNT_* code.
+ *   d_ws          workspace of ch_hull_batch_workspace_bytes(nsets, total).
+ * Returns CH_OK once enqueued; CH_E_INVALID_ARG / CH_E_DEVICE as ch_filter.
+ * Each set's hull follows the conventions of ch_hull exactly.
+ */
+ch_status ch_hull_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
+                        uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
+                        void* d_ws, size_t ws_bytes, void* stream);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around each
  * kernel. While enabled, every ch_* call synchronises its stream before
  * returning. ch_profile_read fills up to cap records and returns the number

@@ -157,6 +157,37 @@ class Context:
             self._raise(st)
         return out[: h.value].copy()
 
+    def hull_batch_async(self, xy, off, hull_idx, hull_count, ws=None):
+        """ch_hull_batch on device tensors: xy (N,2) float32, off (nsets+1)
+        int64 (uint64 offsets), hull_idx (N,) int32, hull_count (nsets,) int32.
+        Enqueues on the current stream and returns."""
+        torch = _torch()
+        n = _check_points(xy)
+        if off.dtype != torch.int64 or not off.is_cuda or off.dim() != 1:
+            raise TypeError("offsets must be a 1-D int64 CUDA tensor")
+        nsets = off.numel() - 1
+        nbytes = self._lib.ch_hull_batch_workspace_bytes(nsets, n)
+        if ws is None:
+            ws = self.workspace(nbytes)
+        st = self._lib.ch_hull_batch(
+            self._h, ctypes.c_void_p(xy.data_ptr()), ctypes.c_void_p(off.data_ptr()), nsets, n,
+            ctypes.c_void_p(hull_idx.data_ptr()), ctypes.c_void_p(hull_count.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+
+    def hull_batch(self, xy, off):
+        """Hulls of the sets [off[s], off[s+1]) of xy: returns (hull_idx,
+        counts) as numpy uint32 arrays; set s's local indices are
+        hull_idx[off[s] : off[s] + counts[s]] when counts[s] is a count."""
+        torch = _torch()
+        n = _check_points(xy)
+        nsets = off.numel() - 1
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device=xy.device)
+        cnt = torch.empty(max(nsets, 1), dtype=torch.int32, device=xy.device)
+        self.hull_batch_async(xy, off, idx, cnt)
+        return idx.cpu().numpy().view(np.uint32)[:n], cnt.cpu().numpy().view(np.uint32)[:nsets]
+
     # -- profiling --------------------------------------------------------
     def profile_enable(self, on: bool = True):
         self._lib.ch_profile_enable(self._h, 1 if on else 0)

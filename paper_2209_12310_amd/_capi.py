@@ -23,6 +23,8 @@ CH_E_CANCELLED = 8
 CH_E_SHUTDOWN = 9
 CH_E_NOT_FOUND = 10
 CH_COUNT_DOMAIN_ERROR = 0xFFFFFFFF
+CH_COUNT_OVERFLOW = 0xFFFFFFFE
+CH_COUNT_INVALID = 0xFFFFFFFD
 CH_MAX_POINTS = 0x7FFFFFFF
 
 STATUS_NAMES = {
@@ -55,6 +57,8 @@ SIGNATURES = {
     "ch_hull_workspace_bytes": (SZ, [U32]),
     "ch_filter": (I32, [P, P, U32, P, P, P, P, P, SZ, P]),
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
+    "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),
+    "ch_hull_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P]),
     "ch_profile_enable": (I32, [P, I32]),
     "ch_profile_reset": (I32, [P]),
     "ch_profile_read": (I32, [P, P, I32, ctypes.POINTER(I32)]),

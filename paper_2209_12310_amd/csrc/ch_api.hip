@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -13,20 +14,26 @@
 #include "ch_internal.hpp"
 
 namespace chk {
-hipError_t launch_ws_init(void* ws, hipStream_t st);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);
-uint32_t reduce_blocks(uint32_t n);
-hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, Header* hdr, Result* res,
-                          double* partials, uint64_t* tstat, uint32_t ntiles2, uint32_t blocks,
-                          hipStream_t st);
+uint32_t reduce_blocks(uint32_t n, uint32_t max_blocks);
+uint32_t filter_blocks(uint32_t n, uint32_t max_blocks);
+hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
+                          uint32_t* part_bad, uint32_t blocks, hipStream_t st);
+hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
+                            Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
+                            hipStream_t st);
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
-                         uint32_t ntiles, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
-                         hipStream_t st);
+                         uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
+                         uint32_t* staging, hipStream_t st);
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
-hipError_t launch_hull_round(int mode, uint32_t grid, const float* xy, const uint32_t* in_idx,
-                             const Rec* in_rec, const uint32_t* in_count, Rec* out_rec,
-                             uint32_t* out_count, uint32_t* tile_ctr, Result* res,
+hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
+                             uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
+                             Rec* staging, hipStream_t st);
+hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
+hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
+                             Rec* out_rec, uint32_t* out_count, uint32_t* tile_ctr,
+                             hipStream_t st);
 hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t max_in,
                             uint64_t* bot, uint64_t* top, uint32_t* cnt, Rec* lst_lo, Rec* lst_up,
                             const Octagon* oct, Result* res, hipStream_t st);
@@ -36,6 +43,13 @@ hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl
                                hipStream_t st);
 hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
                               Result* res, uint32_t* res_idx, hipStream_t st);
+hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
+                                    uint64_t total_points, BatchHdr* bh, SetState* sets,
+                                    SetTile* tiles, Rec* recs, uint32_t grid, hipStream_t st);
+hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
+                                  SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
+                                  uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
+                                  hipStream_t st);
 }  // namespace chk
 
 using namespace chk;
@@ -56,6 +70,8 @@ struct KStat {
 struct ch_ctx {
   int device = 0;
   int cu_count = 0;
+  uint32_t reduce_max_blocks = 1024;  // persistent grid sizes, from the CU count
+  uint32_t filter_max_blocks = 1024;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   std::string err;
   bool prof = false;
@@ -155,30 +171,36 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<unsigned char*>(ws) + off);
 }
 
-// Enqueues ws_init, pass 1 and pass 2. surv / count_out receive the survivors.
+// Enqueues pass 1 (reduce + octagon build) and pass 2 (filter + compaction).
 ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
                      uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
-                     hipStream_t st) {
+                     hipStream_t st, Rec* surv_rec = nullptr, Rec* rec_staging = nullptr) {
   const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
-  const uint32_t ntiles = filter_tiles(n);
   Header* hdr = at<Header>(ws, L.hdr);
   Result* res = at<Result>(ws, L.res);
+  const uint32_t g1 = reduce_blocks(n, ctx->reduce_max_blocks);
+  const uint32_t g2 = filter_blocks(n, ctx->filter_max_blocks);
   hipError_t e;
   {
-    ProfScope p(ctx, st, "ws_init");
-    e = launch_ws_init(ws, st);
-  }
-  if (e != hipSuccess) return hip_fail(ctx, e, "ws_init launch");
-  {
     ProfScope p(ctx, st, "reduce8");
-    e = launch_reduce8(d_xy, n, head, hdr, res, at<double>(ws, L.partials), at<uint64_t>(ws, L.tstat),
-                       ntiles, reduce_blocks(n), st);
+    e = launch_reduce8(d_xy, n, head, at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad), g1,
+                       st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
   {
+    ProfScope p(ctx, st, "oct_build");
+    e = launch_oct_build(at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad), g1, hdr, res,
+                         at<uint64_t>(ws, L.tstat), g2, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
+  {
     ProfScope p(ctx, st, "filter_compact");
-    e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), ntiles, surv, count_out, labels,
-                      st);
+    if (surv_rec)
+      e = launch_filter_rec(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv_rec, count_out,
+                            rec_staging, st);
+    else
+      e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
+                        at<uint32_t>(ws, L.staging), st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "filter launch");
   return CH_OK;
@@ -228,6 +250,19 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
   if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) !=
       hipSuccess)
     ctx->cu_count = 256;
+  ctx->reduce_max_blocks = (uint32_t)ctx->cu_count * 4;
+  if (ctx->reduce_max_blocks > (uint32_t)kReduceMaxBlocks) ctx->reduce_max_blocks = kReduceMaxBlocks;
+  ctx->filter_max_blocks = (uint32_t)ctx->cu_count * 4;
+  if (ctx->filter_max_blocks > (uint32_t)kFilterMaxBlocks) ctx->filter_max_blocks = kFilterMaxBlocks;
+  // Overrides for tuning sweeps.
+  if (const char* e = std::getenv("CH_REDUCE_BLOCKS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= kReduceMaxBlocks) ctx->reduce_max_blocks = (uint32_t)v;
+  }
+  if (const char* e = std::getenv("CH_FILTER_BLOCKS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= kFilterMaxBlocks) ctx->filter_max_blocks = (uint32_t)v;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kResBytes + 4 * kPinIdx,
                     hipHostMallocDefault) != hipSuccess) {
     delete ctx;
@@ -305,9 +340,12 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   Header* hdr = at<Header>(d_ws, L.hdr);
   Result* res = at<Result>(d_ws, L.res);
   uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
-  uint32_t* surv = at<uint32_t>(d_ws, L.surv);
+  Rec* srec = at<Rec>(d_ws, L.surv);
   Rec* rec[2] = {at<Rec>(d_ws, L.recA), at<Rec>(d_ws, L.recB)};
-  if (ch_status s = run_filter(ctx, d_xy, n, surv, &hdr->count, nullptr, d_ws, L, st)) return s;
+  // The survivor records' overflow staging reuses list B (first written by round 1).
+  if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec,
+                               rec[1]))
+    return s;
 
   const Result* hres = reinterpret_cast<const Result*>(ctx->pinned);
   const uint32_t* hidx = reinterpret_cast<const uint32_t*>(ctx->pinned + kResBytes);
@@ -319,39 +357,49 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     return hipStreamSynchronize(st);
   };
 
-  int round = 0;
-  uint32_t grid = (n + kHullTile - 1) / kHullTile;
-  if (grid > (uint32_t)kHullGridMax) grid = kHullGridMax;
+  hipError_t e;
+  {
+    ProfScope p(ctx, st, "hull_final");
+    e = launch_hull_final(srec, &hdr->count, res, res_idx, &hdr->oct, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
+  if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull final");
+  prof_collect(ctx, st);
+  if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
   bool large = false;
+  int round = 0;
   int last_list = -1;  // record list holding the latest round's output
-  while (true) {
-    hipError_t e;
+  while (hres->status != RES_DONE) {
+    if (hres->status != RES_MORE) return fail(ctx, CH_E_DEVICE, "hull status %u", hres->status);
+    const uint32_t cin = hres->cin;
+    uint32_t grid = (cin + kHullTile - 1) / kHullTile;
+    const uint32_t gmax = (uint32_t)ctx->cu_count * 3;
+    if (grid > gmax) grid = gmax;
+    if (grid < 1) grid = 1;
+    const uint32_t* in_count = round == 0 ? &hdr->count : &res->round_cnt[round];
     {
       ProfScope p(ctx, st, round == 0 ? "hull_round0" : "hull_round");
-      e = launch_hull_round(round == 0 ? 0 : 1, grid, d_xy, surv, round ? rec[(round - 1) & 1] : nullptr,
-                            round == 0 ? &hdr->count : &res->round_cnt[round], rec[round & 1],
-                            &res->round_cnt[round + 1], &res->round_tile[round], res, res_idx,
-                            &hdr->oct, st);
+      e = launch_hull_round(grid, round ? rec[(round - 1) & 1] : srec, in_count, rec[round & 1],
+                            &res->round_cnt[round + 1], &res->round_tile[round], st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "hull round launch");
+    {
+      ProfScope p(ctx, st, "hull_final");
+      e = launch_hull_final(rec[round & 1], &res->round_cnt[round + 1], res, res_idx, &hdr->oct, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
     if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull round");
     prof_collect(ctx, st);
-    if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
-    if (hres->status == RES_DONE) break;
-    if (hres->status != RES_MORE) return fail(ctx, CH_E_DEVICE, "hull round status %u", hres->status);
-    // A round that keeps more than half of its input hands over to the
-    // large-hull path.
-    const uint32_t cin = hres->cin;
-    const uint32_t cout = hres->round_cnt[round + 1];
     last_list = round & 1;
     ++round;
+    if (hres->status == RES_DONE) break;
+    // A round that keeps more than half of its input hands over to the
+    // large-hull path.
+    const uint32_t cout = hres->cin;
     if (uint64_t(cout) * 2 > cin || round + 1 >= kMaxRounds) {
       large = true;
       break;
     }
-    grid = (cout + kHullTile - 1) / kHullTile;
-    if (grid > (uint32_t)kHullGridMax) grid = kHullGridMax;
-    if (grid < 1) grid = 1;
   }
 
   if (large) {
@@ -363,7 +411,6 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     Rec* Blo = lstB; Rec* Bup = lstB + chain_cap;
     uint32_t* wcnt = at<uint32_t>(d_ws, L.wcnt);
     const size_t wstride = chain_cap / 4096 + 4;
-    hipError_t e;
     {
       ProfScope p(ctx, st, "col_build");
       e = launch_col_build(rec[last_list], &res->round_cnt[round], cin, at<uint64_t>(d_ws, L.colbot),
@@ -417,6 +464,51 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hull copy");
   }
+  return CH_OK;
+}
+
+size_t ch_hull_batch_workspace_bytes(uint32_t nsets, uint64_t total_points) {
+  return batch_layout(nsets, total_points).total;
+}
+
+ch_status ch_hull_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
+                        uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
+                        void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (nsets == 0) return CH_OK;
+  if (!d_off || !d_hull_count) return fail(ctx, CH_E_INVALID_ARG, "d_off / d_hull_count is NULL");
+  if (total_points >= 0xFFFFFFFFull)
+    return fail(ctx, CH_E_INVALID_ARG, "total_points must stay below 2^32");
+  if (total_points && (!d_xy || !d_hull_idx))
+    return fail(ctx, CH_E_INVALID_ARG, "d_xy / d_hull_idx is NULL");
+  if (reinterpret_cast<uintptr_t>(d_xy) & 15u)
+    return fail(ctx, CH_E_INVALID_ARG, "d_xy must be 16-byte aligned in batch mode");
+  const BatchLayout L = batch_layout(nsets, total_points);
+  if (!d_ws || ws_bytes < L.total)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  BatchHdr* bh = at<BatchHdr>(d_ws, L.hdr);
+  SetState* sets = at<SetState>(d_ws, L.sets);
+  Rec* recA = at<Rec>(d_ws, L.recA);
+  Rec* recB = at<Rec>(d_ws, L.recB);
+  hipError_t e;
+  {
+    ProfScope p(ctx, st, "batch_filter");
+    e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, bh, sets, at<SetTile>(d_ws, L.tiles),
+                                 recA, ctx->filter_max_blocks, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
+  {
+    ProfScope p(ctx, st, "batch_hull");
+    e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
+                               d_hull_idx, d_hull_count, (uint32_t)ctx->cu_count * 3, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch hull launch");
+  prof_collect(ctx, st);
   return CH_OK;
 }
 

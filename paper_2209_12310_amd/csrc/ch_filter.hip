@@ -1,28 +1,36 @@
 // Filtering stage of the heaphull method on gfx950 (CDNA4, wave64).
 //
-// Pass 1 (k_reduce8): one streaming read of the points. Each lane keeps eight
-// running extremes; the four axis extremes and the four Manhattan corners of
-// Sec. III collapse into max/min of four exact fp64 keys, because for points
-// inside the box of the axis extremes the Manhattan distance to a box corner
-// is an affine function of x+y or x-y. The last block to finish builds the
-// octagon (slot order E NE N NW W SW S SE), its exact edge forms and an
-// axis-aligned box inside it for a cheap first test.
+// Pass 1 (k_reduce8 + k_oct_build): one streaming read of the points. Each
+// lane keeps eight running extremes; the four axis extremes and the four
+// Manhattan corners of Sec. III collapse into max/min of four exact fp64 keys,
+// because for points inside the box of the axis extremes the Manhattan
+// distance to a box corner is an affine function of x+y or x-y. One workgroup
+// then builds the octagon (slot order E NE N NW W SW S SE), its exact edge
+// forms and an axis-aligned box inside it for a cheap first test.
 //
 // Pass 2 (k_filter): a second streaming read. Each point is tested against the
 // octagon (Alg. 1/2: keep what lies outside; Sec. I: a point on a side that is
 // not a vertex is discarded). Survivors are compacted in ascending index order
-// in the same pass: ballot + popcount ranks inside a wave, an LDS scan across
-// the waves of a tile, and a decoupled look-back across tiles with tile ids
-// handed out in launch order so that every tile waited on is already running.
+// in the same pass: ballot + popcount ranks inside a wave, contiguous ranges
+// per wave, and one look-back per workgroup over the counts of the earlier
+// workgroups.
 //
 // All predicates are exact: coordinates are multiples of 2^-20 below 1, so the
 // keys (< 2^45 in units of 2^-20) and the edge forms (< 2^42) are integers that
 // fp64 represents exactly, and every fma below rounds nothing.
-#include "ch_internal.hpp"
+#include "ch_device.hpp"
 
 namespace chk {
 
 static constexpr double kShift = 4194304.0;  // 2^22: primary key weight
+
+// Streaming loads of two points (16 B) that bypass cache retention: the
+// points are read once per pass.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
 static constexpr float kGridF = 1048576.0f;  // 2^20
 
 struct Keys {
@@ -131,161 +139,236 @@ __device__ __forceinline__ int64_t orient_i64(int64_t ax, int64_t ay, int64_t bx
   return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
 }
 
-__device__ bool box_inside(const int64_t* vx, const int64_t* vy, int64_t xl, int64_t xh,
-                           int64_t yl, int64_t yh) {
-  if (!(xl < xh && yl < yh)) return false;
-  const int64_t cx[4] = {xl, xh, xh, xl}, cy[4] = {yl, yl, yh, yh};
-  for (int i = 0; i < 8; ++i) {
-    const int j = (i + 1) & 7;
-    for (int c = 0; c < 4; ++c)
-      if (orient_i64(vx[i], vy[i], vx[j], vy[j], cx[c], cy[c]) < 0) return false;
-  }
-  return true;
-}
-
-// Single-thread tail of pass 1: decode the octagon, check the domain, build
-// the edge forms and an inscribed box, and reset the per-call counters.
-__device__ void build_octagon(const Keys& k, Header* hdr, Result* res, uint32_t dom_bad) {
-  Octagon& o = hdr->oct;
-  const double K[8] = {k.mxE, k.mxNE, k.mxN, k.mnSE, k.mnE, k.mnNE, k.mnN, k.mxSE};
-  const int type[8] = {0, 2, 1, 3, 0, 2, 1, 3};
-  int64_t vx[8], vy[8];
-  bool ok = dom_bad == 0;
-  for (int s = 0; s < 8; ++s) {
-    if (!decode_slot(K[s], type[s], vx[s], vy[s])) { ok = false; vx[s] = vy[s] = 0; }
-  }
-  o.status = ok ? 0u : 1u;
-  for (int s = 0; s < 8; ++s) {
-    const int t = (s + 1) & 7;
-    const int64_t ddx = vx[t] - vx[s], ddy = vy[t] - vy[s];
-    o.A[s] = (double)(-ddy) * 1048576.0;
-    o.B[s] = (double)ddx * 1048576.0;
-    o.C[s] = (double)(ddy * vx[s] - ddx * vy[s]);
-    o.vx[s] = (int32_t)vx[s];
-    o.vy[s] = (int32_t)vy[s];
-    hdr->vidx[s] = 0xFFFFFFFFu;
-  }
-  // Inscribed box: centred on the octagon's bounding box with the same aspect
-  // ratio, scaled by the largest factor that keeps all four corners inside
-  // every edge (solved in fp64), then rounded inwards and verified exactly.
-  bool box_ok = false;
-  int64_t xl = 0, xh = 0, yl = 0, yh = 0;
-  if (ok) {
+// The inscribed box is centred on the octagon's bounding box, keeps its aspect
+// ratio, and is scaled by the largest factor t <= 1 that keeps all four
+// corners inside every edge. Lane 4*i + c solves the bound of edge i and
+// corner c in fp64; a wave-wide minimum follows. The result is a candidate
+// only: it is rounded inwards and verified exactly.
+__device__ double box_scale_lane(const int64_t* vx, const int64_t* vy, int lane) {
+  double t = 1.0;
+  if (lane < 32) {
+    const int i = lane >> 2, j = (i + 1) & 7;
+    const int sx = (lane & 1) ? 1 : -1, sy = (lane & 2) ? 1 : -1;
     const double cx = 0.5 * (double)(vx[0] + vx[4]), cy = 0.5 * (double)(vy[2] + vy[6]);
     const double wx = 0.5 * (double)(vx[0] - vx[4]), wy = 0.5 * (double)(vy[2] - vy[6]);
-    double t = 1.0;
-    for (int i = 0; i < 8; ++i) {
-      const int j = (i + 1) & 7;
-      const double ex = (double)(vx[j] - vx[i]), ey = (double)(vy[j] - vy[i]);
-      const double Lc = ex * (cy - (double)vy[i]) - ey * (cx - (double)vx[i]);
-      for (int sx = -1; sx <= 1; sx += 2)
-        for (int sy = -1; sy <= 1; sy += 2) {
-          const double kk = ex * sy * wy - ey * sx * wx;
-          if (kk < 0) t = __builtin_fmin(t, Lc / -kk);
-          else if (Lc < 0) t = -1.0;
-        }
-    }
-    if (t > 0 && wx > 0 && wy > 0) {
-      t *= 0.999999;
-      xl = (int64_t)__builtin_ceil(cx - t * wx);
-      xh = (int64_t)__builtin_floor(cx + t * wx);
-      yl = (int64_t)__builtin_ceil(cy - t * wy);
-      yh = (int64_t)__builtin_floor(cy + t * wy);
-      for (int it = 0; it < 4 && !box_ok; ++it) {
-        box_ok = box_inside(vx, vy, xl, xh, yl, yh);
-        if (!box_ok) { ++xl; --xh; ++yl; --yh; }
-      }
-    }
+    const double ex = (double)(vx[j] - vx[i]), ey = (double)(vy[j] - vy[i]);
+    const double Lc = ex * (cy - (double)vy[i]) - ey * (cx - (double)vx[i]);
+    const double kk = ex * sy * wy - ey * sx * wx;
+    if (kk < 0) t = Lc / -kk;
+    else if (Lc < 0) t = -1.0;
   }
-  o.box_ok = box_ok ? 1u : 0u;
-  if (box_ok) {
-    o.box[0] = (float)xl * (1.0f / kGridF);
-    o.box[1] = (float)xh * (1.0f / kGridF);
-    o.box[2] = (float)yl * (1.0f / kGridF);
-    o.box[3] = (float)yh * (1.0f / kGridF);
-  } else {
-    o.box[0] = 1.0f; o.box[1] = 0.0f; o.box[2] = 1.0f; o.box[3] = 0.0f;  // empty
-  }
-  // Per-call counters used by the kernels that follow in stream order.
-  hdr->tile_ctr = 0;
-  hdr->dom_bad = 0;
-  hdr->count = 0;
-  hdr->col_arrive = 0;
-  res->status = RES_PENDING;
-  res->h = 0;
-  res->lcount = res->ucount = 0;
-  for (int r = 0; r < kMaxRounds; ++r) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
-  for (int r = 0; r < 4; ++r) res->win_cnt[r] = 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t = __builtin_fmin(t, __shfl_xor(t, o));
+  return t;
 }
 
-// Pass 1. head = 1 when xy is 8 mod 16 bytes aligned: point 0 is then handled
-// on its own and the float4 stream starts at point 1.
-__global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
-                                                    uint32_t head, Header* __restrict__ hdr,
-                                                    Result* __restrict__ res,
-                                                    double* __restrict__ partials,
-                                                    uint64_t* __restrict__ tstat, uint32_t ntiles2) {
-  const uint32_t gsize = gridDim.x * blockDim.x;
-  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t i = gtid; i < ntiles2; i += gsize) tstat[i] = 0ull;  // pass-2 look-back state
+// One wave: decode the octagon from the slot keys, check the domain, write
+// the edge forms and the inscribed box to `o`, and reset vidx (may be null).
+// Lanes 0-7 decode one slot each; lanes 0-31 test one (edge, corner) pair each.
+__device__ void octagon_wave(const Keys& k, Octagon& o, uint32_t* vidx, uint32_t dom_bad) {
+  const int lane = threadIdx.x & 63;
+  const double K[8] = {k.mxE, k.mxNE, k.mxN, k.mnSE, k.mnE, k.mnNE, k.mnN, k.mxSE};
+  int64_t mx = 0, my = 0;
+  bool good = true;
+  if (lane < 8) {
+    const int type = (lane == 0 || lane == 4) ? 0 : (lane == 2 || lane == 6) ? 1
+                     : (lane == 1 || lane == 5) ? 2 : 3;
+    double kv = K[0];
+#pragma unroll
+    for (int s = 1; s < 8; ++s) kv = lane == s ? K[s] : kv;
+    good = decode_slot(kv, type, mx, my);
+    if (!good) mx = my = 0;
+  }
+  const bool ok = __ballot(!good) == 0 && dom_bad == 0;
+  int64_t vx[8], vy[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    vx[s] = __shfl(mx, s);
+    vy[s] = __shfl(my, s);
+  }
+  if (lane < 8) {
+    const int t = (lane + 1) & 7;
+    const int64_t ddx = vx[t] - mx, ddy = vy[t] - my;
+    o.A[lane] = (double)(-ddy) * 1048576.0;
+    o.B[lane] = (double)ddx * 1048576.0;
+    o.C[lane] = (double)(ddy * mx - ddx * my);
+    o.vx[lane] = (int32_t)mx;
+    o.vy[lane] = (int32_t)my;
+    if (vidx) vidx[lane] = 0xFFFFFFFFu;
+  }
+  const double t0 = box_scale_lane(vx, vy, lane);
+  bool box_ok = false;
+  int64_t xl = 0, xh = 0, yl = 0, yh = 0;
+  const double cx = 0.5 * (double)(vx[0] + vx[4]), cy = 0.5 * (double)(vy[2] + vy[6]);
+  const double wx = 0.5 * (double)(vx[0] - vx[4]), wy = 0.5 * (double)(vy[2] - vy[6]);
+  if (ok && t0 > 0 && wx > 0 && wy > 0) {
+    const double t = t0 * 0.999999;
+    xl = (int64_t)__builtin_ceil(cx - t * wx);
+    xh = (int64_t)__builtin_floor(cx + t * wx);
+    yl = (int64_t)__builtin_ceil(cy - t * wy);
+    yh = (int64_t)__builtin_floor(cy + t * wy);
+    for (int it = 0; it < 4; ++it) {
+      bool in = true;
+      if (lane < 32) {
+        const int i = lane >> 2, j = (i + 1) & 7;
+        const int64_t px = (lane & 1) ? xh : xl, py = (lane & 2) ? yh : yl;
+        in = orient_i64(vx[i], vy[i], vx[j], vy[j], px, py) >= 0;
+      }
+      box_ok = xl < xh && yl < yh && __ballot(!in) == 0;
+      if (box_ok) break;
+      ++xl; --xh; ++yl; --yh;
+    }
+  }
+  if (lane == 0) {
+    o.status = ok ? 0u : 1u;
+    o.box_ok = box_ok ? 1u : 0u;
+    if (box_ok) {
+      o.box[0] = (float)xl * (1.0f / kGridF);
+      o.box[1] = (float)xh * (1.0f / kGridF);
+      o.box[2] = (float)yl * (1.0f / kGridF);
+      o.box[3] = (float)yh * (1.0f / kGridF);
+    } else {
+      o.box[0] = 1.0f; o.box[1] = 0.0f; o.box[2] = 1.0f; o.box[3] = 0.0f;  // empty
+    }
+  }
+}
 
+// Wave 0 of k_oct_build: the octagon of the single set, then the per-call
+// counters used by the kernels that follow in stream order.
+__device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint32_t dom_bad) {
+  const int lane = threadIdx.x & 63;
+  octagon_wave(k, hdr->oct, hdr->vidx, dom_bad);
+  if (lane == 0) {
+    hdr->tile_ctr = 0;
+    hdr->dom_bad = 0;
+    hdr->count = 0;
+    hdr->col_arrive = 0;
+    res->status = RES_PENDING;
+    res->h = 0;
+    res->lcount = res->ucount = 0;
+  }
+  for (int r = lane; r < kMaxRounds; r += 64) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
+  if (lane < 4) res->win_cnt[lane] = 0;
+}
+
+// Pass 1: persistent grid. Each wave streams batches of kU rows of 64 pairs
+// (kU coalesced 1 KiB loads per batch) and issues the next batch's loads
+// before reducing the current one, so every wave keeps 4-8 KiB in flight.
+// Lanes past the end re-read the last pair: duplicates do not move an
+// extreme. head = 1 when xy is 8 mod 16 bytes aligned: point 0 is then read
+// on its own and the float4 stream starts at point 1. Each block writes its 8
+// keys and a domain flag; k_oct_build combines them.
+constexpr int kU = 4;
+
+__global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
+                                                    uint32_t head, double* __restrict__ partials,
+                                                    uint32_t* __restrict__ part_bad) {
   Keys k;
   keys_init(k);
   bool bad = false;
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
-  const uint32_t npairs = (n - head) >> 1;
-  uint32_t p = gtid;
-  for (; p + 3 * gsize < npairs; p += 4 * gsize) {
-    const float4 a = p4[p], b = p4[p + gsize], c = p4[p + 2 * gsize], d = p4[p + 3 * gsize];
-    keys_add(k, a.x, a.y, bad); keys_add(k, a.z, a.w, bad);
-    keys_add(k, b.x, b.y, bad); keys_add(k, b.z, b.w, bad);
-    keys_add(k, c.x, c.y, bad); keys_add(k, c.z, c.w, bad);
-    keys_add(k, d.x, d.y, bad); keys_add(k, d.z, d.w, bad);
+  const uint32_t nfull = (n - head) >> 1;
+  const int lane = threadIdx.x & 63;
+  const uint32_t gw = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * kWaves;
+  const uint32_t per_batch = kU * 64;
+  const uint32_t nbatch = (nfull + per_batch - 1) / per_batch;
+  if (gw < nbatch) {
+    float4 cur[kU], nxt[kU];
+    uint32_t b = gw;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t q = b * per_batch + u * 64 + lane;
+      cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+    }
+    while (true) {
+      const uint32_t bn = b + nw;
+      const bool more = bn < nbatch;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t q = bn * per_batch + u * 64 + lane;
+          nxt[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        keys_add(k, cur[u].x, cur[u].y, bad);
+        keys_add(k, cur[u].z, cur[u].w, bad);
+      }
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+      b = bn;
+    }
   }
-  for (; p < npairs; p += gsize) {
-    const float4 a = p4[p];
-    keys_add(k, a.x, a.y, bad); keys_add(k, a.z, a.w, bad);
-  }
-  if (gtid == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (head) keys_add(k, xy[0], xy[1], bad);
     if ((n - head) & 1) keys_add(k, xy[2 * (n - 1)], xy[2 * (n - 1) + 1], bad);
   }
-  if (bad) atomicOr(&hdr->dom_bad, 1u);
-
-  block_keys(k);
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    double a[8];
-    keys_to_array(k, a);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(partials) + size_t(blockIdx.x) * 8;
-    for (int i = 0; i < 8; ++i)
-      __hip_atomic_store(dst + i, (uint64_t)__double_as_longlong(a[i]), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const uint32_t prev = __hip_atomic_fetch_add(&hdr->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == gridDim.x - 1;
-  }
+  const uint64_t badmask = __ballot(bad);
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  keys_init(k);
-  const uint64_t* src = reinterpret_cast<const uint64_t*>(partials);
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-    double a[8];
-    for (int i = 0; i < 8; ++i)
-      a[i] = __longlong_as_double((long long)__hip_atomic_load(src + size_t(b) * 8 + i,
-                                                               __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT));
-    Keys o;
-    keys_from_array(o, a);
-    keys_merge(k, o);
-  }
+  if (lane == 0 && badmask) s_bad = 1;
   block_keys(k);
   if (threadIdx.x == 0) {
-    const uint32_t db = __hip_atomic_load(&hdr->dom_bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    build_octagon(k, hdr, res, db);
-    hdr->arrive = 0;
+    keys_to_array(k, partials + size_t(blockIdx.x) * 8);
+    part_bad[blockIdx.x] = s_bad;
+  }
+}
+
+// One workgroup: combine the pass-1 partials (all loads issued up front),
+// build the octagon, and reset every per-call counter and look-back word used
+// by the kernels that follow.
+__global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__ partials,
+                                                      const uint32_t* __restrict__ part_bad,
+                                                      uint32_t nparts, Header* __restrict__ hdr,
+                                                      Result* __restrict__ res,
+                                                      uint64_t* __restrict__ tstat,
+                                                      uint32_t ntstat) {
+  constexpr int kPer = kReduceMaxBlocks / kBlock;
+  Keys k;
+  keys_init(k);
+  uint32_t bad = 0;
+  double4 a[kPer][2];
+  uint32_t bb[kPer];
+  const double4* __restrict__ p4 = reinterpret_cast<const double4*>(partials);
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t b = threadIdx.x + r * kBlock;
+    if (b < nparts) {
+      a[r][0] = p4[2 * b];
+      a[r][1] = p4[2 * b + 1];
+      bb[r] = part_bad[b];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const uint32_t b = threadIdx.x + r * kBlock;
+    if (b < nparts) {
+      const double v[8] = {a[r][0].x, a[r][0].y, a[r][0].z, a[r][0].w,
+                           a[r][1].x, a[r][1].y, a[r][1].z, a[r][1].w};
+      Keys o;
+      keys_from_array(o, v);
+      keys_merge(k, o);
+      bad |= bb[r];
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < ntstat; i += blockDim.x) tstat[i] = 0ull;
+  const uint64_t badmask = __ballot(bad != 0);
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && badmask) s_bad = 1;
+  block_keys(k);
+  if (threadIdx.x < 64) {
+    double v[8];
+    keys_to_array(k, v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = __shfl(v[i], 0);
+    keys_from_array(k, v);
+    build_octagon_wave(k, hdr, res, s_bad);
   }
 }
 
@@ -335,133 +418,207 @@ __device__ __forceinline__ Verdict classify(float x, float y, uint32_t gidx,
 
 __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
-// Pass 2. Grid = filter_tiles(n) blocks; tile ids come from hdr->tile_ctr.
-template <bool LABELS>
+// Pass 2: persistent grid of G2 workgroups. Workgroup ids come from
+// hdr->tile_ctr in start order; workgroup c owns waves 4c..4c+3 and wave k
+// streams the contiguous rows [k*RW, (k+1)*RW) of 64 pairs, so the survivors
+// of the waves, concatenated in wave order, are in ascending index order.
+// A wave stages its survivors in LDS (overflow: in `staging` at the wave's
+// own point range). When the workgroup is done it publishes its count, reads
+// the counts of all earlier workgroups (look-back over at most G2 words, all
+// loaded at once), and copies its survivors to their final place.
+// Survivor payloads: the index alone (ch_filter), or a record with the grid
+// coordinates (the hull pass then never gathers from the point array).
+template <class P>
+__device__ __forceinline__ P make_payload(uint32_t g, float x, float y);
+template <>
+__device__ __forceinline__ uint32_t make_payload<uint32_t>(uint32_t g, float, float) {
+  return g;
+}
+template <>
+__device__ __forceinline__ Rec make_payload<Rec>(uint32_t g, float x, float y) {
+  Rec r;
+  r.x = (int32_t)(x * kGridF);
+  r.y = (int32_t)(y * kGridF);
+  r.i = g;
+  r.pad = 0;
+  return r;
+}
+
+template <class P>
+struct StageCap {
+  static constexpr int value = 8192 / (int)sizeof(P);  // 8 KiB of LDS per wave
+};
+
+template <bool LABELS, class P>
 __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy, uint32_t n,
                                                    uint32_t head, Header* __restrict__ hdr,
-                                                   uint64_t* __restrict__ tstat, uint32_t ntiles,
-                                                   uint32_t* __restrict__ surv,
+                                                   uint64_t* __restrict__ tstat, uint32_t G2,
+                                                   P* __restrict__ surv,
                                                    uint32_t* __restrict__ count_out,
-                                                   uint8_t* __restrict__ labels) {
-  __shared__ uint32_t s_tile, s_head, s_total, s_prefix;
-  __shared__ uint32_t s_off[kPairsPerThread * kWaves];
+                                                   uint8_t* __restrict__ labels,
+                                                   P* __restrict__ staging) {
+  constexpr int kCapW = StageCap<P>::value;
+  __shared__ P s_buf[kWaves][kCapW];
+  __shared__ uint32_t s_chunk, s_prefix, s_total;
+  __shared__ uint32_t s_cnt[kWaves];
   const Octagon* __restrict__ o = &hdr->oct;
   uint32_t* __restrict__ vidx = hdr->vidx;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
-  if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->tile_ctr, 1u);
+  if (threadIdx.x == 0) s_chunk = atomicAdd(&hdr->tile_ctr, 1u);
   __syncthreads();
-  const uint32_t t = s_tile;
+  const uint32_t c = s_chunk;
   if (o->status != 0) {
-    if (t == ntiles - 1 && threadIdx.x == 0) *count_out = kCountDomain;
+    if (c == G2 - 1 && threadIdx.x == 0) *count_out = kCountDomain;
     return;
   }
   const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
   const uint32_t nfull = (n - head) >> 1;
   const bool half = ((n - head) & 1) != 0;
+  const uint32_t npt = nfull + (half ? 1u : 0u);        // pairs including the half pair
+  const uint32_t rows = (npt + 63) / 64;
+  const uint32_t nwaves = G2 * kWaves;
+  const uint32_t rw = (rows + nwaves - 1) / nwaves;     // rows per wave
+  const uint32_t k = c * kWaves + w;
+  const uint32_t r0 = k * rw < rows ? k * rw : rows;
+  const uint32_t r1 = r0 + rw < rows ? r0 + rw : rows;
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
+  const float2* __restrict__ p2 = reinterpret_cast<const float2*>(xy);
+  // Staging slot 0 of wave k is the first point index it owns (0 for wave 0,
+  // which also owns the head point).
+  const uint32_t sbase = k == 0 ? 0u : head + 2u * r0 * 64u;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t cw = 0;  // survivors of this wave so far (wave-uniform)
 
-  float4 v[kPairsPerThread];
-#pragma unroll
-  for (int j = 0; j < kPairsPerThread; ++j) {
-    const uint32_t q = t * kTilePairs + j * kBlock + threadIdx.x;
+  auto put = [&](uint32_t pos, const P& v) {
+    if (pos < (uint32_t)kCapW) s_buf[w][pos] = v;
+    else staging[sbase + pos] = v;
+  };
+
+  if (k == 0 && head && lane == 0) {
+    const Verdict r = classify<LABELS>(xy[0], xy[1], 0u, o, vidx);
+    if (LABELS) labels[0] = r.label;
+    if (r.keep) s_buf[0][0] = make_payload<P>(0u, xy[0], xy[1]);
+    cw = r.keep ? 1u : 0u;
+  }
+  cw = __shfl(cw, 0);
+
+  auto load_row = [&](uint32_t r, float4& v) {
+    const uint32_t q = r * 64 + lane;
     if (q < nfull) {
-      v[j] = p4[q];
+      v = ld_stream(&p4[q]);
     } else if (q == nfull && half) {
-      const float2 u = reinterpret_cast<const float2*>(xy)[head + 2 * q];
-      v[j] = make_float4(u.x, u.y, 0.f, 0.f);
+      const float2 u = p2[head + 2 * q];
+      v = make_float4(u.x, u.y, 0.f, 0.f);
     } else {
-      v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      v = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-  }
+  };
 
-  uint64_t b0[kPairsPerThread], b1[kPairsPerThread];
+  float4 cur[kU], nxt[kU];
+  uint32_t r = r0;
+  if (r < r1) {
 #pragma unroll
-  for (int j = 0; j < kPairsPerThread; ++j) {
-    const uint32_t q = t * kTilePairs + j * kBlock + threadIdx.x;
-    const bool val1 = q < nfull;
-    const bool val0 = val1 || (q == nfull && half);
-    const uint32_t g = head + 2 * q;
-    const float x0 = v[j].x, y0 = v[j].y, x1 = v[j].z, y1 = v[j].w;
-    const bool in0 = (x0 > bxl) & (x0 < bxh) & (y0 > byl) & (y0 < byh);
-    const bool in1 = (x1 > bxl) & (x1 < bxh) & (y1 > byl) & (y1 < byh);
-    const bool need0 = val0 & !in0, need1 = val1 & !in1;
-    Verdict r0{false, 0}, r1{false, 0};
-    if (__ballot(need0 | need1)) {
-      if (need0) r0 = classify<LABELS>(x0, y0, g, o, vidx);
-      if (need1) r1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
-    }
-    b0[j] = __ballot(r0.keep);
-    b1[j] = __ballot(r1.keep);
-    if (LABELS) {
-      if (val0) labels[g] = r0.label;
-      if (val1) labels[g + 1] = r1.label;
-    }
+    for (int u = 0; u < kU; ++u) load_row(r + u < r1 ? r + u : r1 - 1, cur[u]);
   }
-
-  // Tile 0 also owns the unaligned head point (index 0), ranked first.
-  if (threadIdx.x == 0) {
-    uint32_t hk = 0;
-    if (t == 0 && head) {
-      const Verdict r = classify<LABELS>(xy[0], xy[1], 0u, o, vidx);
-      hk = r.keep ? 1u : 0u;
-      if (LABELS) labels[0] = r.label;
-    }
-    s_head = hk;
-  }
-  if (lane == 0) {
+  while (r < r1) {
+    const uint32_t rn = r + kU;
+    const bool more = rn < r1;
+    if (more) {
 #pragma unroll
-    for (int j = 0; j < kPairsPerThread; ++j) s_off[j * kWaves + w] = popc64(b0[j]) + popc64(b1[j]);
+      for (int u = 0; u < kU; ++u) load_row(rn + u < r1 ? rn + u : r1 - 1, nxt[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t row = r + u;
+      if (row < r1) {  // wave-uniform
+        const uint32_t q = row * 64 + lane;
+        const bool val1 = q < nfull;
+        const bool val0 = val1 || (q == nfull && half);
+        const uint32_t g = head + 2 * q;
+        const float x0 = cur[u].x, y0 = cur[u].y, x1 = cur[u].z, y1 = cur[u].w;
+        const bool in0 = (x0 > bxl) & (x0 < bxh) & (y0 > byl) & (y0 < byh);
+        const bool in1 = (x1 > bxl) & (x1 < bxh) & (y1 > byl) & (y1 < byh);
+        const bool need0 = val0 & !in0, need1 = val1 & !in1;
+        Verdict v0{false, 0}, v1{false, 0};
+        if (__ballot(need0 | need1)) {
+          if (need0) v0 = classify<LABELS>(x0, y0, g, o, vidx);
+          if (need1) v1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
+        }
+        if (LABELS) {
+          if (val0) labels[g] = v0.label;
+          if (val1) labels[g + 1] = v1.label;
+        }
+        const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
+        if (b0 | b1) {
+          const uint32_t rank = cw + popc64(b0 & lt) + popc64(b1 & lt);
+          if (v0.keep) put(rank, make_payload<P>(g, x0, y0));
+          if (v1.keep) put(rank + (v0.keep ? 1u : 0u), make_payload<P>(g + 1, x1, y1));
+          cw += popc64(b0) + popc64(b1);
+        }
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+    r = rn;
   }
+  if (lane == 0) s_cnt[w] = cw;
   __syncthreads();
 
-  // Exclusive scan of the (j, wave) group counts in index order, then the
-  // look-back for the tile's global offset; both by wave 0.
+  // Look-back: publish this workgroup's count, then add up every earlier
+  // workgroup's count, stopping at the nearest one that already published
+  // its inclusive prefix.
   if (w == 0) {
-    constexpr int kGroups = kPairsPerThread * kWaves;
-    static_assert(kGroups <= 64, "group scan fits one wave");
-    const uint32_t c = lane < kGroups ? s_off[lane] : 0u;
-    uint32_t incl = c;
+    uint32_t total = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t u = __shfl_up(incl, d);
-      if (lane >= d) incl += u;
-    }
-    const uint32_t hk = s_head;
-    if (lane < kGroups) s_off[lane] = incl - c + hk;
-    const uint32_t total = __shfl(incl, 63) + hk;
-
+    for (int i = 0; i < kWaves; ++i) total += s_cnt[i];
+    if (lane == 0)
+      __hip_atomic_store(&tstat[c], ((c == 0 ? 2ull : 1ull) << 32) | total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
-    if (t == 0) {
-      if (lane == 0)
-        __hip_atomic_store(&tstat[0], (2ull << 32) | total, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (lane == 0)
-        __hip_atomic_store(&tstat[t], (1ull << 32) | total, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      int64_t base = (int64_t)t - 1;
-      while (true) {
-        const int64_t idx = base - lane;
-        uint64_t s = 2ull << 32;  // beyond tile 0: an inclusive zero
+    if (c > 0) {
+      constexpr int kSlots = 16;  // 16 * 64 = 1024 >= G2
+      uint64_t word[kSlots];
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) {
+        const int64_t idx = (int64_t)c - 1 - lane - 64 * i;
+        word[i] = idx >= 0 ? __hip_atomic_load(&tstat[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : (2ull << 32);
+      }
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) {
+        const int64_t idx = (int64_t)c - 1 - lane - 64 * i;
         if (idx >= 0) {
-          s = __hip_atomic_load(&tstat[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          while ((s >> 32) == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            s = __hip_atomic_load(&tstat[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          while ((word[i] >> 32) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            word[i] = __hip_atomic_load(&tstat[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        const uint64_t pm = __ballot((s >> 32) == 2);
-        const int first = pm ? (__ffsll((long long)pm) - 1) : 63;
-        uint64_t contrib = lane <= first ? (uint64_t)(uint32_t)s : 0ull;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) contrib += __shfl_xor(contrib, d);
-        excl += contrib;
-        if (pm) break;
-        base -= 64;
       }
+      // Distance (in workgroups) to the nearest inclusive word.
+      int near = 1 << 30;
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) {
+        const int d = lane + 64 * i;
+        if ((word[i] >> 32) == 2 && d < near) near = d;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const int o2 = __shfl_xor(near, off);
+        near = o2 < near ? o2 : near;
+      }
+      uint64_t sum = 0;
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) {
+        const int d = lane + 64 * i;
+        if (d <= near) sum += (uint32_t)word[i];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      excl = sum;
       if (lane == 0)
-        __hip_atomic_store(&tstat[t], (2ull << 32) | (uint32_t)(excl + total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&tstat[c], (2ull << 32) | (uint32_t)(excl + total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
@@ -470,21 +627,13 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
     }
   }
   __syncthreads();
-
   const uint32_t prefix = s_prefix;
-  if (t == ntiles - 1 && threadIdx.x == 0) *count_out = prefix + s_total;
-  if (threadIdx.x == 0 && s_head) surv[prefix] = 0u;
-  const uint64_t lt = (1ull << lane) - 1ull;
-#pragma unroll
-  for (int j = 0; j < kPairsPerThread; ++j) {
-    if ((b0[j] | b1[j]) == 0ull) continue;
-    const uint32_t q = t * kTilePairs + j * kBlock + threadIdx.x;
-    const uint32_t g = head + 2 * q;
-    const uint32_t base = prefix + s_off[j * kWaves + w] + popc64(b0[j] & lt) + popc64(b1[j] & lt);
-    const uint32_t k0 = (uint32_t)(b0[j] >> lane) & 1u, k1 = (uint32_t)(b1[j] >> lane) & 1u;
-    if (k0) surv[base] = g;
-    if (k1) surv[base + k0] = g + 1;
-  }
+  if (c == G2 - 1 && threadIdx.x == 0) *count_out = prefix + s_total;
+  uint32_t off = prefix;
+  for (int i = 0; i < w; ++i) off += s_cnt[i];
+  const uint32_t nb = cw < (uint32_t)kCapW ? cw : (uint32_t)kCapW;
+  for (uint32_t i = lane; i < nb; i += 64) surv[off + i] = s_buf[w][i];
+  for (uint32_t i = kCapW + lane; i < cw; i += 64) surv[off + i] = staging[sbase + i];
 }
 
 // Copies the octagon (coordinates and smallest indices) to a caller buffer.
@@ -497,57 +646,295 @@ __global__ void k_oct_out(const Header* __restrict__ hdr, int32_t* __restrict__ 
   }
 }
 
-__global__ void k_ws_init(uint32_t* __restrict__ hdr_words, uint32_t nwords) {
-  for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) hdr_words[i] = 0u;
-}
-
 __global__ void k_set_u32(uint32_t* __restrict__ p, uint32_t v) {
   if (threadIdx.x == 0) *p = v;
 }
 
-// ------------------------------------------------------------- launchers
+// ------------------------------------------------------------- batch mode
+//
+// Thousands of independent sets in one stream-ordered sequence of kernels
+// (capturable in a graph, no host synchronisation): a plan kernel cuts every
+// set into tiles of kBatchTile points; pass 1 reduces tiles (workgroups take
+// tiles with a fixed stride, no shared counter) and folds them into the set's
+// keys with 64-bit atomic max on an order-preserving encoding; one wave per
+// set builds its octagon; pass 2 filters tiles and appends survivor records
+// (set-local indices) to the set's own slice of a record buffer.
 
-hipError_t launch_ws_init(void* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(kBlock), 0, st, static_cast<uint32_t*>(ws),
-                     uint32_t((kHdrBytes + kResBytes) / 4));
-  return hipGetLastError();
+// Order-preserving map from fp64 to uint64 (for atomic max on keys).
+__device__ __forceinline__ uint64_t enc_f64(double d) {
+  const uint64_t b = (uint64_t)__double_as_longlong(d);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
+__device__ __forceinline__ double dec_f64(uint64_t e) {
+  const uint64_t b = (e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e;
+  return __longlong_as_double((long long)b);
+}
+
+// One workgroup: tile lists and per-set state. Thread t owns a contiguous
+// group of sets; one exclusive scan gives every group its first tile.
+__global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restrict__ off,
+                                                       uint32_t nsets, uint64_t total_points,
+                                                       BatchHdr* __restrict__ bh,
+                                                       SetState* __restrict__ sets,
+                                                       SetTile* __restrict__ tiles) {
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = (off[0] != 0 || off[nsets] != total_points) ? 1u : 0u;
+  __syncthreads();
+  const uint32_t per = (nsets + kBlock - 1) / kBlock;
+  const uint32_t s0 = threadIdx.x * per;
+  const uint32_t s1 = s0 + per < nsets ? s0 + per : nsets;
+  for (uint32_t s = s0; s < s1; ++s)
+    if (off[s + 1] < off[s]) s_bad = 1u;
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  uint32_t mine = 0;
+  for (uint32_t s = s0; s < s1 && !bad; ++s) {
+    const uint64_t n = off[s + 1] - off[s];
+    mine += (uint32_t)((n + kBatchTile - 1) / kBatchTile);
+  }
+  uint32_t total;
+  uint32_t t = block_excl_scan(mine, total);
+  for (uint32_t s = s0; s < s1; ++s) {
+    const uint32_t a = (uint32_t)off[s], b = bad ? a : (uint32_t)off[s + 1];
+    for (uint32_t p = a; p < b; p += kBatchTile) {
+      SetTile st;
+      st.set = s; st.begin = p; st.end = p + kBatchTile < b ? p + kBatchTile : b; st.pad = 0;
+      tiles[t++] = st;
+    }
+    SetState& ss = sets[s];
+    for (int k = 0; k < 8; ++k) ss.key[k] = 0ull;
+    ss.bad = 0;
+    ss.done = 0;
+    for (int r = 0; r <= kBatchRounds; ++r) ss.cnt[r] = 0;
+  }
+  if (threadIdx.x == 0) {
+    bh->ntiles = total;
+    bh->bad_offsets = bad ? 1u : 0u;
+    for (int r = 0; r <= kBatchRounds; ++r) bh->nround[r] = 0;
+  }
+}
+
+// Iterates the points of [a, b) of a 16-byte aligned point array, two at a
+// time where possible: f(x, y, g) for every point g, spread over the block.
+template <class F>
+__device__ __forceinline__ void for_points(const float* __restrict__ xy, uint32_t a, uint32_t b,
+                                           F&& f) {
+  const uint32_t a2 = a + (a & 1u);
+  const uint32_t npairs = b > a2 ? (b - a2) >> 1 : 0;
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * (size_t)a2);
+  uint32_t p = threadIdx.x;
+  for (; p + 3 * kBlock < npairs; p += 4 * kBlock) {
+    float4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ld_stream(&p4[p + u * kBlock]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t g = a2 + 2 * (p + u * kBlock);
+      f(v[u].x, v[u].y, g);
+      f(v[u].z, v[u].w, g + 1);
+    }
+  }
+  for (; p < npairs; p += kBlock) {
+    const float4 v = ld_stream(&p4[p]);
+    const uint32_t g = a2 + 2 * p;
+    f(v.x, v.y, g);
+    f(v.z, v.w, g + 1);
+  }
+  if (threadIdx.x == 0) {
+    if ((a & 1u) && a < b) f(xy[2 * (size_t)a], xy[2 * (size_t)a + 1], a);
+    const uint32_t last = a2 + 2 * npairs;
+    if (last < b) f(xy[2 * (size_t)last], xy[2 * (size_t)last + 1], last);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_reduce(const float* __restrict__ xy,
+                                                         const BatchHdr* __restrict__ bh,
+                                                         const SetTile* __restrict__ tiles,
+                                                         SetState* __restrict__ sets) {
+  const uint32_t ntiles = bh->ntiles;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const SetTile st = tiles[t];
+    Keys k;
+    keys_init(k);
+    bool bad = false;
+    for_points(xy, st.begin, st.end, [&](float x, float y, uint32_t) { keys_add(k, x, y, bad); });
+    const uint64_t badmask = __ballot(bad);
+    block_keys(k);
+    if (threadIdx.x == 0) {
+      SetState& ss = sets[st.set];
+      const double mx[4] = {k.mxE, k.mxN, k.mxNE, k.mxSE};
+      const double mn[4] = {k.mnE, k.mnN, k.mnNE, k.mnSE};
+      for (int i = 0; i < 4; ++i) {
+        atomicMax((unsigned long long*)&ss.key[i], (unsigned long long)enc_f64(mx[i]));
+        atomicMax((unsigned long long*)&ss.key[4 + i], (unsigned long long)enc_f64(-mn[i]));
+      }
+    }
+    if ((threadIdx.x & 63) == 0 && badmask) atomicOr(&sets[st.set].bad, 1u);
+  }
+}
+
+// One wave per set: decode the set's keys and build its octagon.
+__global__ __launch_bounds__(kBlock) void k_batch_octagon(const uint64_t* __restrict__ off,
+                                                          uint32_t nsets,
+                                                          const BatchHdr* __restrict__ bh,
+                                                          SetState* __restrict__ sets) {
+  const uint32_t s = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (s >= nsets || bh->bad_offsets) return;
+  if (off[s + 1] <= off[s]) return;
+  SetState& ss = sets[s];
+  Keys k;
+  k.mxE = dec_f64(ss.key[0]); k.mxN = dec_f64(ss.key[1]);
+  k.mxNE = dec_f64(ss.key[2]); k.mxSE = dec_f64(ss.key[3]);
+  k.mnE = -dec_f64(ss.key[4]); k.mnN = -dec_f64(ss.key[5]);
+  k.mnNE = -dec_f64(ss.key[6]); k.mnSE = -dec_f64(ss.key[7]);
+  octagon_wave(k, ss.oct, ss.vidx, ss.bad);
+}
+
+// Pass 2 of a tile: exact octagon test, survivors appended as records with
+// set-local indices to recs[off[set] + ...] (one atomic per wave and row).
+__global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict__ xy,
+                                                         const uint64_t* __restrict__ off,
+                                                         const BatchHdr* __restrict__ bh,
+                                                         const SetTile* __restrict__ tiles,
+                                                         SetState* __restrict__ sets,
+                                                         Rec* __restrict__ recs) {
+  const uint32_t ntiles = bh->ntiles;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const SetTile st = tiles[t];
+    SetState& ss = sets[st.set];
+    const Octagon* __restrict__ o = &ss.oct;
+    if (o->status != 0) continue;  // block-uniform
+    const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
+    const uint32_t base = (uint32_t)off[st.set];
+    const uint32_t a = st.begin, b = st.end;
+    const uint32_t a2 = a + (a & 1u);
+    const uint32_t npairs = b > a2 ? (b - a2) >> 1 : 0;
+    const uint32_t nrows = (npairs + 63) / 64;
+    const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * (size_t)a2);
+    for (uint32_t r = w; r < nrows; r += kWaves) {
+      const uint32_t q = r * 64 + lane;
+      const bool val = q < npairs;
+      const float4 v = val ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t g = a2 + 2 * q;
+      const bool in0 = (v.x > bxl) & (v.x < bxh) & (v.y > byl) & (v.y < byh);
+      const bool in1 = (v.z > bxl) & (v.z < bxh) & (v.w > byl) & (v.w < byh);
+      const bool need0 = val & !in0, need1 = val & !in1;
+      Verdict v0{false, 0}, v1{false, 0};
+      if (__ballot(need0 | need1)) {
+        if (need0) v0 = classify<false>(v.x, v.y, g - base, o, ss.vidx);
+        if (need1) v1 = classify<false>(v.z, v.w, g + 1 - base, o, ss.vidx);
+      }
+      const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
+      if (b0 | b1) {
+        uint32_t pos = 0;
+        if (lane == 0) pos = atomicAdd(&ss.cnt[0], popc64(b0) + popc64(b1));
+        pos = __shfl(pos, 0) + popc64(b0 & lt) + popc64(b1 & lt);
+        if (v0.keep) recs[base + pos] = make_payload<Rec>(g - base, v.x, v.y);
+        if (v1.keep) recs[base + pos + (v0.keep ? 1u : 0u)] = make_payload<Rec>(g + 1 - base, v.z, v.w);
+      }
+    }
+    if (threadIdx.x == 0) {
+      const uint32_t last = a2 + 2 * npairs;
+      uint32_t singles[2];
+      int ns = 0;
+      if ((a & 1u) && a < b) singles[ns++] = a;
+      if (last < b) singles[ns++] = last;
+      for (int i = 0; i < ns; ++i) {
+        const uint32_t g = singles[i];
+        const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
+        if (classify<false>(x, y, g - base, o, ss.vidx).keep) {
+          const uint32_t pos = atomicAdd(&ss.cnt[0], 1u);
+          recs[base + pos] = make_payload<Rec>(g - base, x, y);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
 
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, st, p, v);
   return hipGetLastError();
 }
 
-uint32_t reduce_blocks(uint32_t n) {
-  const uint32_t per = kBlock * 16;  // aim for >= 16 points per thread
-  uint32_t b = (n + per - 1) / per;
+// Persistent grid of pass 1: at most `max_blocks`, and no more than needed
+// for one batch per wave.
+uint32_t reduce_blocks(uint32_t n, uint32_t max_blocks) {
+  const uint64_t pairs = (uint64_t(n) + 1) / 2;
+  const uint64_t per_block = uint64_t(kWaves) * kU * 64;
+  uint64_t b = (pairs + per_block - 1) / per_block;
   if (b < 1) b = 1;
-  if (b > (uint32_t)kReduceMaxBlocks) b = kReduceMaxBlocks;
-  return b;
+  if (b > max_blocks) b = max_blocks;
+  return (uint32_t)b;
 }
 
-hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, Header* hdr, Result* res,
-                          double* partials, uint64_t* tstat, uint32_t ntiles2, uint32_t blocks,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, res, partials,
-                     tstat, ntiles2);
+// Persistent grid of pass 2: at most `max_blocks` (and at most 1024, the
+// look-back reach), each wave getting at least one row.
+uint32_t filter_blocks(uint32_t n, uint32_t max_blocks) {
+  const uint64_t rows = ((uint64_t(n) + 1) / 2 + 63) / 64;
+  uint64_t b = (rows + kWaves - 1) / kWaves;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  if (b > 1024) b = 1024;
+  return (uint32_t)b;
+}
+
+hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
+                          uint32_t* part_bad, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
+                            Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_oct_build, dim3(1), dim3(kBlock), 0, st, partials, part_bad, nparts, hdr, res,
+                     tstat, ntstat);
   return hipGetLastError();
 }
 
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
-                         uint32_t ntiles, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
-                         hipStream_t st) {
+                         uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
+                         uint32_t* staging, hipStream_t st) {
   if (labels)
-    hipLaunchKernelGGL(k_filter<true>, dim3(ntiles), dim3(kBlock), 0, st, xy, n, head, hdr, tstat,
-                       ntiles, surv, count_out, labels);
+    hipLaunchKernelGGL((k_filter<true, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
+                       hdr, tstat, blocks, surv, count_out, labels, staging);
   else
-    hipLaunchKernelGGL(k_filter<false>, dim3(ntiles), dim3(kBlock), 0, st, xy, n, head, hdr, tstat,
-                       ntiles, surv, count_out, labels);
+    hipLaunchKernelGGL((k_filter<false, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
+                       hdr, tstat, blocks, surv, count_out, labels, staging);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
+                             uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
+                             Rec* staging, hipStream_t st) {
+  hipLaunchKernelGGL((k_filter<false, Rec>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr,
+                     tstat, blocks, surv, count_out, nullptr, staging);
   return hipGetLastError();
 }
 
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
   hipLaunchKernelGGL(k_oct_out, dim3(1), dim3(64), 0, st, hdr, static_cast<int32_t*>(d_oct));
+  return hipGetLastError();
+}
+
+}  // namespace chk
+
+namespace chk {
+
+hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
+                                    uint64_t total_points, BatchHdr* bh, SetState* sets,
+                                    SetTile* tiles, Rec* recs, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, bh,
+                     sets, tiles);
+  hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(kBlock), 0, st, xy, bh, tiles, sets);
+  hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
+                     nsets, bh, sets);
+  hipLaunchKernelGGL(k_batch_filter, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets,
+                     recs);
   return hipGetLastError();
 }
 

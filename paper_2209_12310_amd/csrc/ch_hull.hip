@@ -1,211 +1,397 @@
 // Device hull pass over the filter's survivors (Alg. 1's per-queue hull,
 // done here on the GPU with Andrew's monotone chain, Table I).
 //
-// Main path -- hull of hulls. The candidate list is cut into tiles of
-// kHullTile items; each workgroup sorts its tile in LDS by (x, y), keeps one
-// entry per distinct coordinate (the smallest index), runs the lower and
-// upper monotone chains and appends the tile's hull to the next round's list.
-// CH(S) = CH(union of the tile hulls), so rounds repeat until one tile holds
-// everything; that tile's hull is the answer.
+// Block hull: a workgroup sorts up to T candidates in LDS by (x, y, position),
+// keeps one entry per distinct coordinate (the smallest index), and builds
+// the lower and upper chains in parallel: every thread chains its own short
+// segment, then log2(256) levels merge neighbouring chains pairwise. A merge
+// pops the left chain's tail and the right chain's head exactly as Andrew's
+// scan would at the junction (both chains are already convex, so no other
+// point can pop), then shifts the right remainder next to the left one.
+//
+// Main path -- hull of hulls. When there are more candidates than one block
+// holds, tiles of kHullTile candidates are reduced to their hulls by many
+// workgroups and the union goes round again: CH(S) = CH(union of tile hulls).
 //
 // Large-hull path -- used when a round stops shrinking the list (a hull with
-// more vertices than a tile holds, or many points in convex position). Only
+// more vertices than a block holds, or many points in convex position). Only
 // the lowest and the highest point of a grid column can be a strict hull
 // vertex, so 64-bit atomics keep per column the bottom and top point; the
 // occupied columns, read in x order, give two x-sorted candidate lists
-// (lower and upper) without any sort. The chains over these lists are
-// computed in windows; windows alternate between two offsets until no window
-// removes anything, at which point every consecutive triple turns the right
-// way and the lists are the chains themselves.
+// (lower and upper) without any sort. Their chains are computed in windows
+// that alternate between two offsets until no window removes anything; then
+// every consecutive triple turns the right way and the lists are the chains.
 //
 // Every orientation test is exact: coordinate differences are below 2^20, so
 // the products are below 2^40 and fp64 holds them and their difference.
-#include "ch_internal.hpp"
+#include "ch_device.hpp"
 
 namespace chk {
 
-__device__ __forceinline__ double cross3(int32_t ax, int32_t ay, int32_t bx, int32_t by, int32_t cx,
-                                         int32_t cy) {
-  const double t = (double)(by - ay) * (double)(cx - ax);
-  return __builtin_fma((double)(bx - ax), (double)(cy - ay), -t);
-}
+#ifdef CH_PHASE_TIMING
+#define CH_MARK(res, k) \
+  do { if (threadIdx.x == 0) (res)->tphase[k] = __builtin_amdgcn_s_memrealtime(); } while (0)
+#else
+#define CH_MARK(res, k) do { } while (0)
+#endif
 
-// Block-wide exclusive scan of one value per thread (all threads call it).
-__device__ uint32_t block_excl_scan(uint32_t v, uint32_t& total) {
-  __shared__ uint32_t s_w[kWaves];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t u = __shfl_up(incl, d);
-    if (lane >= d) incl += u;
-  }
-  if (lane == 63) s_w[w] = incl;
-  __syncthreads();
-  uint32_t off = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) {
-    const uint32_t x = s_w[i];
-    if (i < w) off += x;
-    tot += x;
-  }
-  __syncthreads();
-  total = tot;
-  return off + incl - v;
-}
-
-// One monotone chain over `nparts` consecutive parts; part p holds len[p]
-// points (1 when len is null) at src[start0 + p*stride ...]. The stack goes to
-// dst starting at start0; src may equal dst because the stack never runs
-// ahead of the points already read. LOWER keeps strict left turns (the lower
-// chain, left to right), otherwise strict right turns (the upper chain, left
-// to right). Returns the stack height.
+// Sequential monotone chain of src[s0, s0+len) onto a stack at dst[s0...];
+// src may equal dst (the stack never overtakes the read position).
 template <bool LOWER>
-__device__ int chain_parts(const int32_t* sx, const int32_t* sy, const uint32_t* si, int32_t* dx,
-                           int32_t* dy, uint32_t* di, uint32_t start0, uint32_t stride, int nparts,
-                           const uint16_t* len) {
+__device__ int seg_chain(const int32_t* sx, const int32_t* sy, const uint32_t* si, int32_t* dx,
+                         int32_t* dy, uint32_t* di, uint32_t s0, int len) {
   int top = 0;
   int32_t ax = 0, ay = 0, bx = 0, by = 0;  // the two topmost stack points
-  for (int p = 0; p < nparts; ++p) {
-    const uint32_t pos = start0 + (uint32_t)p * stride;
-    const int L = len ? (int)len[p] : 1;
-    for (int k = 0; k < L; ++k) {
-      const int32_t x = sx[pos + k], y = sy[pos + k];
-      const uint32_t id = si[pos + k];
-      while (top >= 2) {
-        const double cr = cross3(ax, ay, bx, by, x, y);
-        if (LOWER ? (cr <= 0.0) : (cr >= 0.0)) {
-          --top;
-          bx = ax; by = ay;
-          if (top >= 2) { ax = dx[start0 + top - 2]; ay = dy[start0 + top - 2]; }
-        } else {
-          break;
-        }
-      }
-      dx[start0 + top] = x; dy[start0 + top] = y; di[start0 + top] = id;
-      ++top;
-      ax = bx; ay = by; bx = x; by = y;
+  for (int k = 0; k < len; ++k) {
+    const int32_t x = sx[s0 + k], y = sy[s0 + k];
+    const uint32_t id = si[s0 + k];
+    while (top >= 2 && bad_turn<LOWER>(ax, ay, bx, by, x, y)) {
+      --top;
+      bx = ax; by = ay;
+      if (top >= 2) { ax = dx[s0 + top - 2]; ay = dy[s0 + top - 2]; }
     }
+    dx[s0 + top] = x; dy[s0 + top] = y; di[s0 + top] = id;
+    ++top;
+    ax = bx; ay = by; bx = x; by = y;
   }
   return top;
+}
+
+// One side's chain of u x-sorted distinct points (src), written to dst[0..len):
+// per-thread segment chains, then pairwise merges up a binary tree. MAXC
+// bounds the elements one thread moves per merge (ceil(S/2), S = u/256).
+// All threads must call it; returns the chain length.
+template <bool LOWER, int MAXC>
+__device__ uint32_t par_chain(const int32_t* sx, const int32_t* sy, const uint32_t* si, int32_t* dx,
+                              int32_t* dy, uint32_t* di, uint32_t u, uint16_t* cnt, int32_t* wij) {
+  // Segments of at least kMinSeg points: fewer merge levels for small inputs.
+  constexpr uint32_t kMinSeg = 2 * MAXC < 8 ? 2 * MAXC : 8;
+  uint32_t S = (u + kBlock - 1) / kBlock;
+  if (S < kMinSeg) S = kMinSeg;
+  const uint32_t nseg = (u + S - 1) / S;
+  const uint32_t t = threadIdx.x;
+  {
+    const uint32_t s0 = t * S;
+    const uint32_t s1 = s0 + S < u ? s0 + S : u;
+    cnt[t] = (uint16_t)seg_chain<LOWER>(sx, sy, si, dx, dy, di, s0, s1 > s0 ? (int)(s1 - s0) : 0);
+  }
+  __syncthreads();
+  for (uint32_t half = 1; half < nseg; half <<= 1) {
+    const uint32_t npairs = kBlock / (2 * half);
+    if (t < npairs) {
+      const uint32_t ls = 2 * t * half * S, rs = (2 * t + 1) * half * S;
+      const int nl = cnt[2 * t * half], nr = cnt[(2 * t + 1) * half];
+      int i = nl - 1, j = 0;
+      if (nl > 0 && nr > 0) {
+        int32_t a1x = dx[ls + i], a1y = dy[ls + i];
+        int32_t a0x = i > 0 ? dx[ls + i - 1] : 0, a0y = i > 0 ? dy[ls + i - 1] : 0;
+        int32_t b0x = dx[rs], b0y = dy[rs];
+        int32_t b1x = nr > 1 ? dx[rs + 1] : 0, b1y = nr > 1 ? dy[rs + 1] : 0;
+        while (true) {
+          bool ch = false;
+          while (i > 0 && bad_turn<LOWER>(a0x, a0y, a1x, a1y, b0x, b0y)) {
+            --i;
+            a1x = a0x; a1y = a0y;
+            if (i > 0) { a0x = dx[ls + i - 1]; a0y = dy[ls + i - 1]; }
+            ch = true;
+          }
+          while (j + 1 < nr && bad_turn<LOWER>(a1x, a1y, b0x, b0y, b1x, b1y)) {
+            ++j;
+            b0x = b1x; b0y = b1y;
+            if (j + 1 < nr) { b1x = dx[rs + j + 1]; b1y = dy[rs + j + 1]; }
+            ch = true;
+          }
+          if (!ch) break;
+        }
+      }
+      wij[2 * t] = i;
+      wij[2 * t + 1] = j;
+    }
+    __syncthreads();
+    const uint32_t tpp = 2 * half;  // threads per pair
+    const uint32_t m = t / tpp, tl = t % tpp;
+    const uint32_t ls = 2 * m * half * S, rs = (2 * m + 1) * half * S;
+    const int nl = cnt[2 * m * half], nr = cnt[(2 * m + 1) * half];
+    const int i = wij[2 * m], j = wij[2 * m + 1];
+    const int ncopy = (nl > 0 && nr > 0) ? nr - j : 0;
+    int32_t vx[MAXC], vy[MAXC];
+    uint32_t vi[MAXC];
+#pragma unroll
+    for (int e = 0; e < MAXC; ++e) {
+      const int p = (int)tl + e * (int)tpp;
+      if (p < ncopy) { vx[e] = dx[rs + j + p]; vy[e] = dy[rs + j + p]; vi[e] = di[rs + j + p]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < MAXC; ++e) {
+      const int p = (int)tl + e * (int)tpp;
+      if (p < ncopy) { dx[ls + i + 1 + p] = vx[e]; dy[ls + i + 1 + p] = vy[e]; di[ls + i + 1 + p] = vi[e]; }
+    }
+    if (tl == 0 && nl > 0) cnt[2 * m * half] = (uint16_t)(i + 1 + ncopy);
+    __syncthreads();
+  }
+  return cnt[0];
+}
+
+// Lower chain of (px, py, pi)[0..ul) and upper chain of (ux, uy, ui)[0..uu),
+// both x-sorted, each built in place: level 0 chains one segment of each side
+// per thread; each merge level walks lower pairs on threads [0, 128) and upper
+// pairs on threads [128, 256), sharing the barriers.
+template <int MAXC>
+__device__ void dual_chain(int32_t* px, int32_t* py, uint32_t* pi, uint32_t ul, int32_t* ux,
+                           int32_t* uy, uint32_t* ui, uint32_t uu, uint16_t* cnt_l,
+                           uint16_t* cnt_u, int32_t* wij_l, int32_t* wij_u, uint32_t& nl,
+                           uint32_t& nu) {
+  constexpr uint32_t kMinSeg = 2 * MAXC < 8 ? 2 * MAXC : 8;
+  uint32_t SL = (ul + kBlock - 1) / kBlock, SU = (uu + kBlock - 1) / kBlock;
+  if (SL < kMinSeg) SL = kMinSeg;
+  if (SU < kMinSeg) SU = kMinSeg;
+  const uint32_t nseg_l = (ul + SL - 1) / SL, nseg_u = (uu + SU - 1) / SU;
+  const uint32_t nseg = nseg_l > nseg_u ? nseg_l : nseg_u;
+  const uint32_t t = threadIdx.x;
+  {
+    uint32_t s0 = t * SL, s1 = s0 + SL < ul ? s0 + SL : ul;
+    cnt_l[t] = (uint16_t)seg_chain<true>(px, py, pi, px, py, pi, s0, s1 > s0 ? (int)(s1 - s0) : 0);
+    s0 = t * SU;
+    s1 = s0 + SU < uu ? s0 + SU : uu;
+    cnt_u[t] = (uint16_t)seg_chain<false>(ux, uy, ui, ux, uy, ui, s0, s1 > s0 ? (int)(s1 - s0) : 0);
+  }
+  __syncthreads();
+  for (uint32_t half = 1; half < nseg; half <<= 1) {
+    const uint32_t npairs = kBlock / (2 * half);
+    {
+      const bool lower = t < 128;
+      const uint32_t m = lower ? t : t - 128;
+      if (m < npairs) {
+        int32_t* dx = lower ? px : ux;
+        int32_t* dy = lower ? py : uy;
+        const uint16_t* cnt = lower ? cnt_l : cnt_u;
+        const uint32_t S = lower ? SL : SU;
+        const uint32_t ls = 2 * m * half * S, rs = (2 * m + 1) * half * S;
+        const int nl2 = cnt[2 * m * half], nr = cnt[(2 * m + 1) * half];
+        int i = nl2 - 1, j = 0;
+        if (nl2 > 0 && nr > 0) {
+          // Two left points and two right points stay in registers.
+          int32_t a1x = dx[ls + i], a1y = dy[ls + i];
+          int32_t a0x = i > 0 ? dx[ls + i - 1] : 0, a0y = i > 0 ? dy[ls + i - 1] : 0;
+          int32_t b0x = dx[rs], b0y = dy[rs];
+          int32_t b1x = nr > 1 ? dx[rs + 1] : 0, b1y = nr > 1 ? dy[rs + 1] : 0;
+          while (true) {
+            bool ch = false;
+            while (i > 0 && (lower ? bad_turn<true>(a0x, a0y, a1x, a1y, b0x, b0y)
+                                   : bad_turn<false>(a0x, a0y, a1x, a1y, b0x, b0y))) {
+              --i;
+              a1x = a0x; a1y = a0y;
+              if (i > 0) { a0x = dx[ls + i - 1]; a0y = dy[ls + i - 1]; }
+              ch = true;
+            }
+            while (j + 1 < nr && (lower ? bad_turn<true>(a1x, a1y, b0x, b0y, b1x, b1y)
+                                        : bad_turn<false>(a1x, a1y, b0x, b0y, b1x, b1y))) {
+              ++j;
+              b0x = b1x; b0y = b1y;
+              if (j + 1 < nr) { b1x = dx[rs + j + 1]; b1y = dy[rs + j + 1]; }
+              ch = true;
+            }
+            if (!ch) break;
+          }
+        }
+        int32_t* wij = lower ? wij_l : wij_u;
+        wij[2 * m] = i;
+        wij[2 * m + 1] = j;
+      }
+    }
+    __syncthreads();
+    const uint32_t tpp = 2 * half;  // threads per pair
+    const uint32_t m = t / tpp, tl = t % tpp;
+    int ncopy[2], ii[2], nlv[2];
+    uint32_t dst0[2];
+    int32_t vx[2][MAXC], vy[2][MAXC];
+    uint32_t vi[2][MAXC];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const uint16_t* cnt = side == 0 ? cnt_l : cnt_u;
+      const int32_t* wij = side == 0 ? wij_l : wij_u;
+      const int32_t* dx = side == 0 ? px : ux;
+      const int32_t* dy = side == 0 ? py : uy;
+      const uint32_t* di = side == 0 ? pi : ui;
+      const uint32_t S = side == 0 ? SL : SU;
+      const uint32_t ls = 2 * m * half * S, rs = (2 * m + 1) * half * S;
+      nlv[side] = cnt[2 * m * half];
+      const int nr = cnt[(2 * m + 1) * half];
+      ii[side] = wij[2 * m];
+      const int jj = wij[2 * m + 1];
+      ncopy[side] = (nlv[side] > 0 && nr > 0) ? nr - jj : 0;
+      dst0[side] = ls + ii[side] + 1;
+#pragma unroll
+      for (int e = 0; e < MAXC; ++e) {
+        const int p = (int)tl + e * (int)tpp;
+        if (p < ncopy[side]) {
+          vx[side][e] = dx[rs + jj + p];
+          vy[side][e] = dy[rs + jj + p];
+          vi[side][e] = di[rs + jj + p];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int32_t* dx = side == 0 ? px : ux;
+      int32_t* dy = side == 0 ? py : uy;
+      uint32_t* di = side == 0 ? pi : ui;
+#pragma unroll
+      for (int e = 0; e < MAXC; ++e) {
+        const int p = (int)tl + e * (int)tpp;
+        if (p < ncopy[side]) {
+          dx[dst0[side] + p] = vx[side][e]; dy[dst0[side] + p] = vy[side][e]; di[dst0[side] + p] = vi[side][e];
+        }
+      }
+      if (tl == 0 && nlv[side] > 0)
+        (side == 0 ? cnt_l : cnt_u)[2 * m * half] = (uint16_t)(ii[side] + 1 + ncopy[side]);
+    }
+    __syncthreads();
+  }
+  nl = cnt_l[0];
+  nu = cnt_u[0];
 }
 
 template <int T>
 struct HullSmem {
   union {
-    uint64_t key[T];                 // sort keys: x<<44 | y<<24 | position
-    struct { int32_t ux[T], uy[T]; } u;  // upper chains (after compaction)
+    uint64_t key[T];                     // sort keys: x<<44 | y<<24 | position
+    struct { int32_t ux[T], uy[T]; } u;  // upper chain (after compaction)
   } a;
   union {
-    uint32_t pidx[T];                // point index per input position
+    uint32_t pidx[T];                    // point index per input position
     uint32_t ui[T];
   } b;
-  int32_t px[T], py[T];              // distinct sorted points, then lower chains
+  int32_t px[T], py[T];                  // distinct sorted points, then the lower chain
   uint32_t pi[T];
-  uint16_t n1[kBlock], n2[16];
-  uint32_t misc[4];
+  uint16_t cnt[kBlock], cnt2[kBlock];
+  int32_t wij[kBlock], wij2[kBlock];
 };
 
-// LDS of the window kernels: one x-sorted window and the chain bookkeeping.
 template <int T>
 struct WinSmem {
   int32_t px[T], py[T];
   uint32_t pi[T];
-  uint16_t n1[kBlock], n2[16];
-  uint32_t misc[4];
+  uint16_t cnt[kBlock];
+  int32_t wij[kBlock];
 };
 
-// One side's chain over u x-sorted distinct points in three levels: 256
-// segments (one per thread), 16 groups of 16 segments, one group of groups.
-// Level 1 reads (sx, sy, si) and writes the segment chains to (dx, dy, di);
-// levels 2 and 3 work in place in (dx, dy, di). All threads must call it.
-// Returns the chain length; the chain is (dx, dy, di)[0..len).
-template <bool LOWER>
-__device__ uint32_t chain3(const int32_t* sx, const int32_t* sy, const uint32_t* si, int32_t* dx,
-                           int32_t* dy, uint32_t* di, uint32_t u, uint16_t* n1, uint16_t* n2,
-                           uint32_t* out) {
-  const uint32_t S = (u + kBlock - 1) / kBlock;
-  {
-    const uint32_t s0 = threadIdx.x * S;
-    const uint32_t s1 = s0 + S < u ? s0 + S : u;
-    const int len = s1 > s0 ? (int)(s1 - s0) : 0;
-    n1[threadIdx.x] = (uint16_t)chain_parts<LOWER>(sx, sy, si, dx, dy, di, s0, 1, len, nullptr);
-  }
-  __syncthreads();
-  if (threadIdx.x < 16) {
-    const int g = threadIdx.x;
-    n2[g] = (uint16_t)chain_parts<LOWER>(dx, dy, di, dx, dy, di, 16u * g * S, S, 16, &n1[16 * g]);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) *out = (uint32_t)chain_parts<LOWER>(dx, dy, di, dx, dy, di, 0, 16u * S, 16, n2);
-  __syncthreads();
-  return *out;
-}
-
-// Lower and upper chains of the u distinct sorted points in sm.px/py/pi. On
-// return the lower chain is px/py/pi[0..nl) and the upper chain is
-// a.u.ux/uy, b.ui[0..nu). The upper chain is built first because the lower
-// one overwrites its input.
 template <int T>
-__device__ void block_chains(HullSmem<T>& sm, uint32_t u, uint32_t& nl, uint32_t& nu) {
-  nu = chain3<false>(sm.px, sm.py, sm.pi, sm.a.u.ux, sm.a.u.uy, sm.b.ui, u, sm.n1, sm.n2, &sm.misc[1]);
-  nl = chain3<true>(sm.px, sm.py, sm.pi, sm.px, sm.py, sm.pi, u, sm.n1, sm.n2, &sm.misc[0]);
-}
+constexpr int maxc() { return (T / kBlock + 1) / 2; }
 
-// Hull of `cnt` items starting at `base`. MODE 0: items are point indices
-// (coordinates gathered from xy); MODE 1: items are records. Returns h; the
+// Directions of the pre-filter polygon: 16 small-integer vectors in
+// counter-clockwise order (0, 22, 45, 68, 90, ... degrees). Dot products with
+// grid points stay below 7 * 2^20, exact in int32.
+__constant__ int8_t kDirX[16] = {1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2, 0, 2, 1, 5};
+__constant__ int8_t kDirY[16] = {0, 2, 1, 5, 1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2};
+
+// Hull of the `cnt` records starting at in_rec[base]. Returns h; the
 // counter-clockwise hull is element k of hull_elem().
-template <int T, int MODE>
-__device__ uint32_t tile_hull(HullSmem<T>& sm, const float* __restrict__ xy,
-                              const uint32_t* __restrict__ in_idx, const Rec* __restrict__ in_rec,
-                              uint32_t base, uint32_t cnt, uint32_t& nl, uint32_t& nu) {
-  uint32_t P2 = kBlock;
-  while (P2 < cnt) P2 <<= 1;
-  for (uint32_t i = threadIdx.x; i < P2; i += kBlock) {
-    if (i < cnt) {
-      int32_t kx, ky;
-      uint32_t id;
-      if (MODE == 0) {
-        id = in_idx[base + i];
-        const float2 p = reinterpret_cast<const float2*>(xy)[id];
-        kx = (int32_t)(p.x * 1048576.0f);
-        ky = (int32_t)(p.y * 1048576.0f);
-      } else {
-        const Rec r = in_rec[base + i];
-        kx = r.x; ky = r.y; id = r.i;
+//
+// Before sorting, the candidates are filtered once more by the rule of the
+// octagon stage, with a finer polygon: the candidates' own extreme points in
+// 16 directions. Every vertex of that polygon is a candidate, so a candidate
+// inside it (or on a side without being a vertex) is not a strict hull vertex
+// of the candidates and can be dropped.
+template <int T>
+__device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, uint32_t base,
+                              uint32_t cnt, uint32_t& nl, uint32_t& nu, Result* tm = nullptr) {
+  constexpr uint32_t E = T / kBlock;  // items per thread: i = threadIdx.x + e * kBlock
+  __shared__ uint64_t s_ext[kWaves][16];
+  __shared__ int32_t s_vx[16], s_vy[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // Load the records (raw input kept in px/py/pi until compaction).
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    const Rec r = in_rec[base + i];
+    sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
+  }
+  __syncthreads();
+  if (tm) CH_MARK(tm, 2);
+  // Extreme position per direction: max of (dot, -position) per thread, then
+  // per wave (DPP), then over the waves.
+  {
+    uint64_t best[16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) best[d] = 0ull;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+      const int32_t x = sm.px[i], y = sm.py[i];
+#pragma unroll
+      for (int d = 0; d < 16; ++d) {
+        const int32_t dot = kDirX[d] * x + kDirY[d] * y + (1 << 23);
+        const uint64_t key = ((uint64_t)(uint32_t)dot << 32) | (0xFFFFFFFFu - i);
+        best[d] = key > best[d] ? key : best[d];
       }
-      sm.a.key[i] = ((uint64_t)(uint32_t)kx << 44) | ((uint64_t)(uint32_t)ky << 24) | i;
-      sm.b.pidx[i] = id;
-    } else {
-      sm.a.key[i] = ~0ull;
+    }
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+      const uint64_t m = wave_max_u64(best[d]);
+      if (lane == 0) s_ext[w][d] = m;
     }
   }
   __syncthreads();
-  // Bitonic sort of P2 keys.
-  for (uint32_t k = 2; k <= P2; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P2 / 2; i += kBlock) {
-        const uint32_t a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-        const uint32_t b = a | j;
-        const uint64_t ka = sm.a.key[a], kb = sm.a.key[b];
-        const bool up = (a & k) == 0;
-        if ((ka > kb) == up) { sm.a.key[a] = kb; sm.a.key[b] = ka; }
+  if (tm) CH_MARK(tm, 9);
+  if (threadIdx.x < 16) {
+    uint64_t b = s_ext[0][threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < kWaves; ++q) b = s_ext[q][threadIdx.x] > b ? s_ext[q][threadIdx.x] : b;
+    const uint32_t p = 0xFFFFFFFFu - (uint32_t)b;
+    s_vx[threadIdx.x] = cnt ? sm.px[p] : 0;
+    s_vy[threadIdx.x] = cnt ? sm.py[p] : 0;
+  }
+  __syncthreads();
+  // Keep a candidate outside some polygon side, or equal to a vertex.
+  uint32_t keepmask = 0, nkeep = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    const uint32_t i = threadIdx.x + e * kBlock;
+    if (i < cnt) {
+      const int32_t x = sm.px[i], y = sm.py[i];
+      bool keep = false;
+#pragma unroll
+      for (int d = 0; d < 16; ++d) {
+        const int d2 = (d + 1) & 15;
+        const int32_t ax = s_vx[d], ay = s_vy[d], bx = s_vx[d2], by = s_vy[d2];
+        keep |= cross3(ax, ay, bx, by, x, y) < 0.0;
+        keep |= (x == ax) & (y == ay);
       }
-      __syncthreads();
+      if (keep) { keepmask |= 1u << e; ++nkeep; }
     }
   }
-  // One entry per distinct coordinate, carrying the smallest index.
-  const uint32_t E = P2 / kBlock;
-  const uint32_t i0 = threadIdx.x * E;
-  uint32_t nfirst = 0;
+  if (tm) CH_MARK(tm, 10);
+  uint32_t kept;
+  uint32_t kpos = block_excl_scan(nkeep, kept);
+  if (tm) CH_MARK(tm, 11);
+  uint32_t P2 = kBlock;
+  while (P2 < kept) P2 <<= 1;
+#pragma unroll
   for (uint32_t e = 0; e < E; ++e) {
-    const uint32_t i = i0 + e;
+    if (keepmask & (1u << e)) {
+      const uint32_t i = threadIdx.x + e * kBlock;
+      sm.a.key[kpos] = ((uint64_t)(uint32_t)sm.px[i] << 44) | ((uint64_t)(uint32_t)sm.py[i] << 24) | kpos;
+      sm.b.pidx[kpos] = sm.pi[i];
+      ++kpos;
+    }
+  }
+  for (uint32_t i = kept + threadIdx.x; i < P2; i += kBlock) sm.a.key[i] = ~0ull;
+  cnt = kept;
+  __syncthreads();
+  if (tm) CH_MARK(tm, 3);
+  bitonic_sort(sm.a.key, P2);
+  if (tm) CH_MARK(tm, 4);
+  // One entry per distinct coordinate, carrying the smallest index.
+  const uint32_t E2 = P2 / kBlock;
+  const uint32_t j0 = threadIdx.x * E2;
+  uint32_t nfirst = 0;
+  for (uint32_t e = 0; e < E2; ++e) {
+    const uint32_t i = j0 + e;
     if (i < cnt && (i == 0 || (sm.a.key[i - 1] >> 24) != (sm.a.key[i] >> 24))) ++nfirst;
   }
   uint32_t u;
   uint32_t pos = block_excl_scan(nfirst, u);
-  for (uint32_t e = 0; e < E; ++e) {
-    const uint32_t i = i0 + e;
+  for (uint32_t e = 0; e < E2; ++e) {
+    const uint32_t i = j0 + e;
     if (i < cnt && (i == 0 || (sm.a.key[i - 1] >> 24) != (sm.a.key[i] >> 24))) {
       const uint64_t kk = sm.a.key[i];
       const uint64_t c = kk >> 24;
@@ -221,8 +407,47 @@ __device__ uint32_t tile_hull(HullSmem<T>& sm, const float* __restrict__ xy,
     }
   }
   __syncthreads();
+  if (tm) CH_MARK(tm, 5);
   if (u == 0) { nl = nu = 0; return 0; }
-  block_chains<T>(sm, u, nl, nu);
+  // Split by the line from the lexicographic minimum to the maximum: a point
+  // strictly above it cannot be on the lower chain, one strictly below cannot
+  // be on the upper chain (Andrew's chains both run between these two ends).
+  // Lower candidates stay in px/py/pi, upper ones move to ux/uy/ui.
+  uint32_t ul, uu;
+  {
+    constexpr uint32_t EM = T / kBlock;
+    const uint32_t Eu = (u + kBlock - 1) / kBlock;
+    const uint32_t q0 = threadIdx.x * Eu;
+    const int32_t x0 = sm.px[0], y0 = sm.py[0], x1 = sm.px[u - 1], y1 = sm.py[u - 1];
+    int32_t rx[EM], ry[EM];
+    uint32_t ri[EM], side = 0;  // bit 2e: lower candidate, bit 2e+1: upper candidate
+    uint32_t nlo = 0, nup = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < EM; ++e) {
+      const uint32_t q = q0 + e;
+      if (e < Eu && q < u) {
+        rx[e] = sm.px[q]; ry[e] = sm.py[q]; ri[e] = sm.pi[q];
+        const double c = cross3(x0, y0, x1, y1, rx[e], ry[e]);
+        const bool end = q == 0 || q == u - 1;
+        const bool lo = end || c < 0.0, up = end || c > 0.0;
+        side |= (lo ? 1u : 0u) << (2 * e);
+        side |= (up ? 1u : 0u) << (2 * e + 1);
+        nlo += lo; nup += up;
+      }
+    }
+    uint32_t plo = block_excl_scan(nlo, ul);
+    uint32_t pup = block_excl_scan(nup, uu);
+#pragma unroll
+    for (uint32_t e = 0; e < EM; ++e) {
+      if (side & (1u << (2 * e))) { sm.px[plo] = rx[e]; sm.py[plo] = ry[e]; sm.pi[plo] = ri[e]; ++plo; }
+      if (side & (2u << (2 * e))) { sm.a.u.ux[pup] = rx[e]; sm.a.u.uy[pup] = ry[e]; sm.b.ui[pup] = ri[e]; ++pup; }
+    }
+    __syncthreads();
+  }
+  dual_chain<maxc<T>()>(sm.px, sm.py, sm.pi, ul, sm.a.u.ux, sm.a.u.uy, sm.b.ui, uu, sm.cnt,
+                        sm.cnt2, sm.wij, sm.wij2, nl, nu);
+  if (tm) CH_MARK(tm, 6);
+  if (tm) CH_MARK(tm, 7);
   return nl + (nu > 2 ? nu - 2 : 0);
 }
 
@@ -241,38 +466,48 @@ __device__ __forceinline__ Rec hull_elem(const HullSmem<T>& sm, uint32_t k, uint
   return r;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_hull_round(const float* __restrict__ xy,
-                                                       const uint32_t* __restrict__ in_idx,
-                                                       const Rec* __restrict__ in_rec,
+// One workgroup: the hull of all candidates when they fit (status DONE),
+// otherwise status MORE with the candidate count in res->cin.
+__global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ in_rec,
                                                        const uint32_t* __restrict__ in_count,
-                                                       Rec* __restrict__ out_rec,
-                                                       uint32_t* __restrict__ out_count,
-                                                       uint32_t* __restrict__ tile_ctr,
                                                        Result* __restrict__ res,
                                                        uint32_t* __restrict__ res_idx,
                                                        const Octagon* __restrict__ oct) {
-  __shared__ HullSmem<kHullTile> sm;
-  __shared__ uint32_t s_tile, s_base;
+  __shared__ HullSmem<kFinalTile> sm;
+  CH_MARK(res, 0);
   if (oct->status != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) res->status = RES_DOMAIN;
+    if (threadIdx.x == 0) res->status = RES_DOMAIN;
     return;
   }
   const uint32_t c = *in_count;
-  if (blockIdx.x == 0 && threadIdx.x == 0) res->cin = c;
-  uint32_t nl, nu;
-  if (c <= (uint32_t)kHullTile) {
-    if (blockIdx.x != 0) return;
-    const uint32_t h = tile_hull<kHullTile, MODE>(sm, xy, in_idx, in_rec, 0, c, nl, nu);
-    for (uint32_t k = threadIdx.x; k < h; k += kBlock) res_idx[k] = hull_elem(sm, k, nl, nu).i;
-    if (threadIdx.x == 0) {
-      res->h = h;
-      res->status = RES_DONE;
-    }
+  CH_MARK(res, 1);
+  if (threadIdx.x == 0) res->cin = c;
+  if (c > (uint32_t)kFinalTile) {
+    if (threadIdx.x == 0) res->status = RES_MORE;
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) res->status = RES_MORE;
+  uint32_t nl, nu;
+  const uint32_t h = tile_hull<kFinalTile>(sm, in_rec, 0, c, nl, nu, res);
+  for (uint32_t k = threadIdx.x; k < h; k += kBlock) res_idx[k] = hull_elem(sm, k, nl, nu).i;
+  CH_MARK(res, 8);
+  if (threadIdx.x == 0) {
+    res->h = h;
+    res->status = RES_DONE;
+  }
+}
+
+// Many workgroups: tiles of kHullTile candidates to tile hulls, appended to
+// out_rec (order between tiles is immaterial: the next round sorts again).
+__global__ __launch_bounds__(kBlock) void k_hull_round(const Rec* __restrict__ in_rec,
+                                                       const uint32_t* __restrict__ in_count,
+                                                       Rec* __restrict__ out_rec,
+                                                       uint32_t* __restrict__ out_count,
+                                                       uint32_t* __restrict__ tile_ctr) {
+  __shared__ HullSmem<kHullTile> sm;
+  __shared__ uint32_t s_tile, s_base;
+  const uint32_t c = *in_count;
   const uint32_t ntiles = (c + kHullTile - 1) / kHullTile;
+  uint32_t nl, nu;
   while (true) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
@@ -280,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_hull_round(const float* __restrict__
     if (tile >= ntiles) break;
     const uint32_t base = tile * kHullTile;
     const uint32_t cnt = c - base < (uint32_t)kHullTile ? c - base : (uint32_t)kHullTile;
-    const uint32_t h = tile_hull<kHullTile, MODE>(sm, xy, in_idx, in_rec, base, cnt, nl, nu);
+    const uint32_t h = tile_hull<kHullTile>(sm, in_rec, base, cnt, nl, nu);
     if (threadIdx.x == 0) s_base = atomicAdd(out_count, h);
     __syncthreads();
     const uint32_t ob = s_base;
@@ -379,13 +614,12 @@ __global__ __launch_bounds__(kBlock) void k_col_emit(const uint64_t* __restrict_
   }
 }
 
-// Chain of one x-sorted, distinct window held in LDS (px/py/pi), in place.
-template <int T, bool LOWER>
-__device__ uint32_t window_chain(WinSmem<T>& sm, uint32_t u) {
-  return chain3<LOWER>(sm.px, sm.py, sm.pi, sm.px, sm.py, sm.pi, u, sm.n1, sm.n2, &sm.misc[0]);
-}
-
 constexpr int kWin = 4096;
+
+template <bool LOWER>
+__device__ uint32_t window_chain(WinSmem<kWin>& sm, uint32_t u) {
+  return par_chain<LOWER, maxc<kWin>()>(sm.px, sm.py, sm.pi, sm.px, sm.py, sm.pi, u, sm.cnt, sm.wij);
+}
 
 // One window round over the lower list (blocks [0, nwl)) and the upper list
 // (blocks [nwl, nwl + nwu)). Window k covers [k*W - shift, (k+1)*W - shift).
@@ -413,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src_l
     sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
   }
   __syncthreads();
-  const uint32_t h = lower ? window_chain<kWin, true>(sm, u) : window_chain<kWin, false>(sm, u);
+  const uint32_t h = lower ? window_chain<true>(sm, u) : window_chain<false>(sm, u);
   for (uint32_t i = threadIdx.x; i < h; i += kBlock) {
     Rec r;
     r.x = sm.px[i]; r.y = sm.py[i]; r.i = sm.pi[i]; r.pad = 0;
@@ -468,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_large_final(const Rec* __restrict__ 
       sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
     }
     __syncthreads();
-    nl = window_chain<kWin, true>(sm, cl);
+    nl = window_chain<true>(sm, cl);
     for (uint32_t i = threadIdx.x; i < nl; i += kBlock) res_idx[i] = sm.pi[i];
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < cu; i += kBlock) {
@@ -476,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_large_final(const Rec* __restrict__ 
       sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
     }
     __syncthreads();
-    nu = window_chain<kWin, false>(sm, cu);
+    nu = window_chain<false>(sm, cu);
     for (uint32_t k = threadIdx.x; k + 2 < nu; k += kBlock) res_idx[nl + k] = sm.pi[nu - 2 - k];
   } else {
     for (uint32_t i = threadIdx.x; i < nl; i += kBlock) res_idx[i] = lo_lst[i].i;
@@ -488,18 +722,112 @@ __global__ __launch_bounds__(kBlock) void k_large_final(const Rec* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------- batch mode
+
+// Hull of every set whose candidates fit one block (<= T); a set still above
+// that waits for the next tile-hull round, or is reported as an overflow after
+// the last one (which runs with the larger block). Workgroups take sets with a
+// fixed stride.
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_batch_final(const uint64_t* __restrict__ off,
+                                                        uint32_t nsets,
+                                                        const BatchHdr* __restrict__ bh,
+                                                        SetState* __restrict__ sets, int stage,
+                                                        const Rec* __restrict__ recs,
+                                                        uint32_t* __restrict__ hull_idx,
+                                                        uint32_t* __restrict__ hull_count,
+                                                        int last) {
+  __shared__ HullSmem<T> sm;
+  const bool bad_off = bh->bad_offsets != 0;
+  for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
+    SetState& ss = sets[s];
+    if (ss.done) continue;
+    if (bad_off) {
+      if (threadIdx.x == 0) { hull_count[s] = kCountInvalid; ss.done = 1; }
+      continue;
+    }
+    const uint32_t a = (uint32_t)off[s];
+    const uint32_t n = (uint32_t)(off[s + 1] - off[s]);
+    if (n == 0 || ss.oct.status != 0) {
+      if (threadIdx.x == 0) { hull_count[s] = n == 0 ? 0u : kCountDomain; ss.done = 1; }
+      continue;
+    }
+    const uint32_t c = ss.cnt[stage];
+    if (c > (uint32_t)T) {
+      if (last && threadIdx.x == 0) { hull_count[s] = kCountOverflow; ss.done = 1; }
+      continue;
+    }
+    uint32_t nl, nu;
+    const uint32_t h = tile_hull<T>(sm, recs + a, 0, c, nl, nu);
+    for (uint32_t k = threadIdx.x; k < h; k += kBlock) hull_idx[a + k] = hull_elem(sm, k, nl, nu).i;
+    if (threadIdx.x == 0) { hull_count[s] = h; ss.done = 1; }
+    __syncthreads();
+  }
+}
+
+// One workgroup: tiles of kHullTile candidates for every unfinished set.
+__global__ __launch_bounds__(kBlock) void k_batch_round_plan(const uint64_t* __restrict__ off,
+                                                             uint32_t nsets,
+                                                             BatchHdr* __restrict__ bh,
+                                                             SetState* __restrict__ sets,
+                                                             int stage,
+                                                             SetTile* __restrict__ rtiles) {
+  const uint32_t per = (nsets + kBlock - 1) / kBlock;
+  const uint32_t s0 = threadIdx.x * per;
+  const uint32_t s1 = s0 + per < nsets ? s0 + per : nsets;
+  uint32_t mine = 0;
+  for (uint32_t s = s0; s < s1; ++s)
+    if (!sets[s].done) mine += (sets[s].cnt[stage] + kHullTile - 1) / kHullTile;
+  uint32_t total;
+  uint32_t t = block_excl_scan(mine, total);
+  for (uint32_t s = s0; s < s1; ++s) {
+    if (sets[s].done) continue;
+    const uint32_t a = (uint32_t)off[s], c = sets[s].cnt[stage];
+    for (uint32_t p = 0; p < c; p += kHullTile) {
+      SetTile st;
+      st.set = s; st.begin = a + p; st.end = a + (p + kHullTile < c ? p + kHullTile : c); st.pad = 0;
+      rtiles[t++] = st;
+    }
+    sets[s].cnt[stage + 1] = 0;
+  }
+  if (threadIdx.x == 0) bh->nround[stage] = total;
+}
+
+// Tile hulls of one round, appended to the set's slice of the next buffer.
+__global__ __launch_bounds__(kBlock) void k_batch_round(const uint64_t* __restrict__ off,
+                                                        const BatchHdr* __restrict__ bh, int stage,
+                                                        const SetTile* __restrict__ rtiles,
+                                                        SetState* __restrict__ sets,
+                                                        const Rec* __restrict__ in,
+                                                        Rec* __restrict__ out) {
+  __shared__ HullSmem<kHullTile> sm;
+  __shared__ uint32_t s_base;
+  const uint32_t nt = bh->nround[stage];
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const SetTile st = rtiles[t];
+    uint32_t nl, nu;
+    const uint32_t h = tile_hull<kHullTile>(sm, in, st.begin, st.end - st.begin, nl, nu);
+    if (threadIdx.x == 0) s_base = (uint32_t)off[st.set] + atomicAdd(&sets[st.set].cnt[stage + 1], h);
+    __syncthreads();
+    const uint32_t ob = s_base;
+    for (uint32_t k = threadIdx.x; k < h; k += kBlock) out[ob + k] = hull_elem(sm, k, nl, nu);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- launchers
 
-hipError_t launch_hull_round(int mode, uint32_t grid, const float* xy, const uint32_t* in_idx,
-                             const Rec* in_rec, const uint32_t* in_count, Rec* out_rec,
-                             uint32_t* out_count, uint32_t* tile_ctr, Result* res,
+hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st) {
-  if (mode == 0)
-    hipLaunchKernelGGL(k_hull_round<0>, dim3(grid), dim3(kBlock), 0, st, xy, in_idx, in_rec,
-                       in_count, out_rec, out_count, tile_ctr, res, res_idx, oct);
-  else
-    hipLaunchKernelGGL(k_hull_round<1>, dim3(grid), dim3(kBlock), 0, st, xy, in_idx, in_rec,
-                       in_count, out_rec, out_count, tile_ctr, res, res_idx, oct);
+  hipLaunchKernelGGL(k_hull_final, dim3(1), dim3(kBlock), 0, st, in_rec, in_count, res, res_idx, oct);
+  return hipGetLastError();
+}
+
+hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
+                             Rec* out_rec, uint32_t* out_count, uint32_t* tile_ctr,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_hull_round, dim3(grid), dim3(kBlock), 0, st, in_rec, in_count, out_rec,
+                     out_count, tile_ctr);
   return hipGetLastError();
 }
 
@@ -540,6 +868,32 @@ hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_
                               Result* res, uint32_t* res_idx, hipStream_t st) {
   hipLaunchKernelGGL(k_large_final, dim3(1), dim3(kBlock), 0, st, lo, up, cl, cu, single, res,
                      res_idx);
+  return hipGetLastError();
+}
+
+}  // namespace chk
+
+namespace chk {
+
+hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
+                                  SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
+                                  uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
+                                  hipStream_t st) {
+  Rec* buf[2] = {recA, recB};
+  hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                     sets, 0, recA, hull_idx, hull_count, 0);
+  for (int r = 0; r < kBatchRounds; ++r) {
+    hipLaunchKernelGGL(k_batch_round_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, bh, sets, r,
+                       rtiles);
+    hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,
+                       buf[r & 1], buf[(r + 1) & 1]);
+    if (r + 1 < kBatchRounds)
+      hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, 0);
+    else
+      hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, 1);
+  }
   return hipGetLastError();
 }
 

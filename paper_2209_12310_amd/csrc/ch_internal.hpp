@@ -11,17 +11,13 @@ namespace chk {
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 
-// Pass 1 (extreme-key reduction).
-constexpr int kReduceMaxBlocks = 2048;
-
-// Pass 2 (octagon test + ordered compaction): 8 float4 loads = 16 points per
-// thread per tile.
-constexpr int kPairsPerThread = 8;
-constexpr uint32_t kTilePairs = kBlock * kPairsPerThread;  // 2048 pairs
-constexpr uint32_t kTilePoints = 2 * kTilePairs;           // 4096 points
+// Pass 1 (extreme-key reduction) and pass 2 (filter): persistent grids.
+constexpr int kReduceMaxBlocks = 4096;
+constexpr int kFilterMaxBlocks = 1024;   // the look-back reads at most 1024 words
 
 // Hull rounds.
 constexpr int kHullTile = 2048;        // items per tile hull (LDS resident)
+constexpr int kFinalTile = 4096;       // items the single-workgroup final hull takes
 constexpr int kHullGridMax = 1024;
 constexpr int kMaxRounds = 48;
 constexpr uint32_t kHullCapMax = 1u << 21;  // strict vertices of a hull on the grid
@@ -71,6 +67,7 @@ struct Result {
   uint32_t round_cnt[kMaxRounds];   // records written by round r (index r+1 = output of round r)
   uint32_t round_tile[kMaxRounds];  // dynamic tile counter of round r
   uint32_t win_cnt[4];              // window-round outputs (lower, upper) per parity
+  uint64_t tphase[12];              // shader-clock marks (builds with CH_PHASE_TIMING only)
 };
 
 struct Rec {           // a candidate hull point: grid coordinates + index
@@ -85,18 +82,11 @@ static_assert(sizeof(Result) <= kResBytes, "result too large");
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline uint32_t filter_tiles(uint32_t n) {
-  // Pairs after the (optional) unaligned head point, half pair included.
-  uint64_t pairs = (uint64_t(n) + 1) / 2;
-  uint64_t t = (pairs + kTilePairs - 1) / kTilePairs;
-  return t ? uint32_t(t) : 1u;
-}
-
 inline uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) : kHullCapMax; }
 
 // Workspace layout. ch_filter uses the prefix up to `filter_end`.
 struct Layout {
-  size_t hdr, res, res_idx, partials, tstat, filter_end;
+  size_t hdr, res, res_idx, partials, part_bad, tstat, staging, filter_end;
   size_t surv, recA, recB, colbot, coltop, colcnt, lstA, lstB, wcnt, total;
 };
 
@@ -107,17 +97,21 @@ inline Layout layout(uint32_t n) {
   L.res = o;       o += kResBytes;
   L.res_idx = o;   o = align_up(o + size_t(hull_cap(n)) * 4, 256);
   L.partials = o;  o = align_up(o + size_t(kReduceMaxBlocks) * 8 * sizeof(double), 256);
-  L.tstat = o;     o = align_up(o + size_t(filter_tiles(n)) * 8, 256);
-  L.filter_end = o;
+  L.part_bad = o;  o = align_up(o + size_t(kReduceMaxBlocks) * 4, 256);
+  L.tstat = o;     o = align_up(o + size_t(kFilterMaxBlocks) * 8, 256);
   size_t m = n ? n : 1;
-  L.surv = o;      o = align_up(o + m * 4, 256);
-  if (n <= (uint32_t)kHullTile) {  // one tile: no further rounds, no large-hull path
-    L.recA = L.recB = L.colbot = L.coltop = L.colcnt = L.lstA = L.lstB = L.wcnt = o;
+  L.staging = o;   o = align_up(o + m * 4, 256);
+  L.filter_end = o;
+  // ch_hull: survivor records, then two record lists for the rounds (list B
+  // doubles as the filter's overflow staging for the survivor records).
+  L.surv = o;      o = align_up(o + m * sizeof(Rec), 256);
+  L.recA = o;      o = align_up(o + m * sizeof(Rec), 256);
+  L.recB = o;      o = align_up(o + m * sizeof(Rec), 256);
+  if (n <= (uint32_t)kFinalTile) {  // one workgroup: no rounds, no large-hull path
+    L.colbot = L.coltop = L.colcnt = L.lstA = L.lstB = L.wcnt = o;
     L.total = o;
     return L;
   }
-  L.recA = o;      o = align_up(o + m * sizeof(Rec), 256);
-  L.recB = o;      o = align_up(o + m * sizeof(Rec), 256);
   L.colbot = o;    o = align_up(o + size_t(kColumns) * 8, 256);
   L.coltop = o;    o = align_up(o + size_t(kColumns) * 8, 256);
   L.colcnt = o;    o = align_up(o + size_t(kColBlocks) * 2 * 4, 256);
@@ -126,6 +120,54 @@ inline Layout layout(uint32_t n) {
   L.lstA = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
   L.lstB = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
   L.wcnt = o;      o = align_up(o + 2 * (chain_cap / kHullTile + 4) * 4, 256);
+  L.total = o;
+  return L;
+}
+
+// ---------------------------------------------------------------- batch mode
+constexpr uint32_t kBatchTile = 8192;     // points per pass-1/pass-2 tile of one set
+constexpr int kBatchRounds = 4;           // tile-hull rounds for sets with many survivors
+constexpr uint32_t kCountOverflow = 0xFFFFFFFEu;
+constexpr uint32_t kCountInvalid = 0xFFFFFFFDu;
+
+struct SetTile {       // points [begin, end) of set `set` (global indices)
+  uint32_t set, begin, end, pad;
+};
+
+struct BatchHdr {
+  uint32_t ntiles;                   // pass tiles (plan kernel)
+  uint32_t bad_offsets;              // offsets not non-decreasing or not ending at the total
+  uint32_t nround[kBatchRounds + 1]; // hull-round tiles per round
+  uint32_t pad[10];
+};
+
+// Per-set state, one struct per set.
+struct SetState {
+  uint64_t key[8];     // order-preserving encodings of the 8 slot keys (max)
+  uint32_t bad;        // domain flag
+  uint32_t done;       // hull written
+  uint32_t cnt[kBatchRounds + 1];  // candidates after the filter / after round r
+  uint32_t vidx[8];    // smallest index per octagon slot (kept for the shared classifier)
+  uint32_t pad[16 - 2 - (kBatchRounds + 1) - 8];
+  Octagon oct;
+};
+
+struct BatchLayout {
+  size_t hdr, sets, tiles, rtiles, recA, recB, total;
+};
+
+inline BatchLayout batch_layout(uint32_t nsets, uint64_t total_points) {
+  BatchLayout L{};
+  size_t o = 0;
+  const size_t ntiles = total_points / kBatchTile + nsets + 1;
+  const size_t nrt = total_points / 2048 + nsets + 1;
+  L.hdr = o;    o = align_up(o + sizeof(BatchHdr), 256);
+  L.sets = o;   o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SetState), 256);
+  L.tiles = o;  o = align_up(o + ntiles * sizeof(SetTile), 256);
+  L.rtiles = o; o = align_up(o + nrt * sizeof(SetTile), 256);
+  const size_t m = total_points ? total_points : 1;
+  L.recA = o;   o = align_up(o + m * sizeof(Rec), 256);
+  L.recB = o;   o = align_up(o + m * sizeof(Rec), 256);
   L.total = o;
   return L;
 }
