@@ -78,6 +78,160 @@ def cpu_baseline(xy, budget_s: float = 12.0):
                       f"to_grid + extremes + octagon filter + monotone chain"}
 
 
+def pct(vals, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(vals, dtype=np.float64), q))
+
+
+def bench_batch(ctx, steps: int, warmup: int) -> dict:
+    """Batched mode on 4096 sets (log-uniform sizes in [1e3, 1e6], kinds
+    uniform / normal / annulus 0.49-0.5, seed 3): one ch_hull_batch call per
+    step, timed with events on the launch stream; compared with one ch_hull
+    call per set on the same device-resident points."""
+    import numpy as np
+    import torch
+
+    from paper_2209_12310_amd import workloads
+    log("generating batch_4096")
+    xy, off, kinds = workloads.batch_sets(4096, 3)
+    n = xy.shape[0]
+    nsets = off.size - 1
+    t = torch.from_numpy(xy).to("cuda:0")
+    o = torch.from_numpy(off.astype(np.int64)).to("cuda:0")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    cnt = torch.empty(nsets, dtype=torch.int32, device="cuda:0")
+    ws = ctx.workspace(ctx._lib.ch_hull_batch_workspace_bytes(nsets, n))
+    for _ in range(warmup):
+        ctx.hull_batch_async(t, o, idx, cnt, ws)
+    torch.cuda.synchronize()
+    counts = cnt.cpu().numpy().view(np.uint32)
+    assert (counts < 0xFFFFFFF0).all(), "batch returned an error code"
+    lat = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        ctx.hull_batch_async(t, o, idx, cnt, ws)
+        b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    # Plain mode: one synchronous ch_hull per set.
+    log("plain mode: one ch_hull per set")
+    for s in range(min(64, nsets)):
+        ctx.hull(t[int(off[s]): int(off[s + 1])])
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for s in range(nsets):
+        ctx.hull(t[int(off[s]): int(off[s + 1])])
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - tp
+    ms = float(np.mean(lat))
+    return {"workload": "batch_4096", "sets": nsets, "points": n, "steps": steps,
+            "ms_per_batch": round(ms, 3), "wall_ms_per_batch": round(wall * 1e3, 3),
+            "hulls_per_s": round(nsets / (ms * 1e-3), 1),
+            "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+            "batch_p50_ms": round(pct(lat, 50), 3), "batch_p99_ms": round(pct(lat, 99), 3),
+            "plain_ms": round(plain * 1e3, 1), "plain_hulls_per_s": round(nsets / plain, 1),
+            "speedup_vs_plain": round(plain / (ms * 1e-3), 2),
+            "kinds": {k: kinds.count(k) for k in sorted(set(kinds))}}
+
+
+def _serve_views(pools, sizes, kinds, seeds):
+    """Request payloads: windows of the pinned per-kind pools (offset drawn
+    from the request's seed), so no request data is generated while timing."""
+    views = []
+    for n, k, sd in zip(sizes, kinds, seeds):
+        pool = pools[k]
+        o = int(sd) % (pool.shape[0] - int(n) + 1)
+        views.append(pool[o: o + int(n)])
+    return views
+
+
+def bench_serve(ctx, duration_s: float = 8.0, arena_gb: int = 64, streams: int = 4) -> dict:
+    """Serving: Poisson arrivals of host-resident requests (sizes log-uniform
+    in [1e2, 1e7], kinds uniform / normal / wide annulus, seed 4) through the
+    ch_serve server; latency = completion - scheduled arrival, including
+    queueing and the host-to-device copy. The rate is 0.7 x the capacity
+    measured on a saturated burst. Compared with plain mode: the same trace
+    solved one request at a time (copy, then ch_hull) on one stream."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2209_12310_amd import workloads
+    pool_n = 10_000_000
+    log("serve: pinned request pools")
+    pools = {k: torch.from_numpy(workloads.by_kind(k, pool_n, 90 + i)).pin_memory()
+             for i, k in enumerate(("uniform", "normal", "annulus_wide"))}
+    arena = torch.empty(arena_gb << 30, dtype=torch.uint8, device="cuda:0")
+    srv = ctx.serve(arena, n_streams=streams)
+    try:
+        # Capacity on a saturated burst.
+        _, bs, bk, bseed = workloads.serve_trace(1e9, 1e9, seed=5, max_requests=1500)
+        burst = _serve_views(pools, bs, bk, bseed)
+        log(f"serve: saturated burst of {len(burst)} requests")
+        t0 = time.monotonic_ns()
+        tick = [srv.submit(v) for v in burst]
+        last = max(int(srv.wait(t)[1][2]) for t in tick)
+        capacity = len(burst) / ((last - t0) * 1e-9)
+        rate = 0.7 * capacity
+        times, sizes, kinds, seeds = workloads.serve_trace(rate, duration_s, seed=4)
+        views = _serve_views(pools, sizes, kinds, seeds)
+        log(f"serve: {len(views)} requests at {rate:.0f}/s for {duration_s} s")
+        q: "queue.Queue" = queue.Queue()
+        start = time.monotonic_ns() + 50_000_000
+        sched = start + (np.asarray(times) * 1e9).astype(np.int64)
+
+        def submitter():
+            for i, v in enumerate(views):
+                d = (int(sched[i]) - time.monotonic_ns()) * 1e-9
+                if d > 0:
+                    time.sleep(d)
+                q.put(srv.submit(v))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat, done_max = [], 0
+        for i in range(len(views)):
+            _, tns = srv.wait(q.get())
+            lat.append((int(tns[2]) - int(sched[i])) * 1e-3)
+            done_max = max(done_max, int(tns[2]))
+        th.join()
+        st = srv.stats()
+    finally:
+        srv.stop()
+    del arena
+    # Plain mode on the same trace: one request at a time.
+    log("serve: plain mode")
+    dev = torch.empty((int(max(sizes)), 2), dtype=torch.float32, device="cuda:0")
+    plat = []
+    pstart = time.monotonic_ns() + 50_000_000
+    psched = pstart + (np.asarray(times) * 1e9).astype(np.int64)
+    for i, v in enumerate(views):
+        d = (int(psched[i]) - time.monotonic_ns()) * 1e-9
+        if d > 0:
+            time.sleep(d)
+        n = v.shape[0]
+        dev[:n].copy_(v, non_blocking=True)
+        ctx.hull(dev[:n])
+        plat.append((time.monotonic_ns() - int(psched[i])) * 1e-3)
+    pend = time.monotonic_ns()
+    return {"workload": "serve_poisson", "requests": len(views), "rate_hz": round(rate, 1),
+            "duration_s": duration_s, "streams": streams, "arena_gb": arena_gb,
+            "mean_points": round(float(np.mean(sizes)), 1),
+            "capacity_hulls_per_s": round(capacity, 1),
+            "hulls_per_s": round(len(views) / ((done_max - start) * 1e-9), 1),
+            "p50_us": round(pct(lat, 50), 1), "p99_us": round(pct(lat, 99), 1),
+            "batches": st["batches"],
+            "plain_hulls_per_s": round(len(views) / ((pend - pstart) * 1e-9), 1),
+            "plain_p50_us": round(pct(plat, 50), 1), "plain_p99_us": round(pct(plat, 99), 1),
+            "input": "pinned host memory, copied to the device inside the measured latency"}
+
+
 def copy_calibration(nbytes: int = 800_000_000, reps: int = 3) -> None:
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -95,6 +249,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -128,18 +284,26 @@ def main() -> int:
     torch.cuda.synchronize()
 
     log(f"timed {args.steps} steps")
-    ctx.profile_reset()
-    ctx.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         hull = ctx.hull(t)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ctx.profile_enable(False)
-    stats = ctx.profile_read()
     ms = elapsed / args.steps * 1e3
     value = n / (ms * 1e-3) / 1e6
+
+    # Kernel durations: a second region of the same steps with the library's
+    # HIP events recorded on the launch stream around every kernel (they add
+    # their own gaps, so the end-to-end figure above is taken without them).
+    log(f"kernel timing {args.steps} steps")
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    for _ in range(args.steps):
+        ctx.hull(t)
+    torch.cuda.synchronize()
+    ctx.profile_enable(False)
+    stats = ctx.profile_read()
 
     kernels = {k: {"launches": v[0], "mean_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
                for k, v in stats.items() if v[0]}
@@ -179,6 +343,13 @@ def main() -> int:
         "roofline": roofline,
         "kernels": kernels,
     }
+    del t
+    torch.cuda.synchronize()
+    if not args.no_batch:
+        out["batch"] = bench_batch(ctx, max(5, min(args.steps, 20)), 1)
+        torch.cuda.synchronize()
+    if not args.no_serve:
+        out["serve"] = bench_serve(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(xy)

@@ -160,6 +160,77 @@ ch_status ch_hull_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, u
                         uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
                         void* d_ws, size_t ws_bytes, void* stream);
 
+/*
+ * Serving: a request is one point set in host memory; the server copies it to
+ * the device, solves it with other pending requests in one ch_hull_batch call
+ * (continuous batching over several streams) and hands the hull back. Not in
+ * the paper, which solves one set per call (Alg. 1); every request's hull
+ * follows the conventions of ch_hull exactly.
+ *
+ * Device memory: the caller's arena of arena_bytes, split evenly into one
+ * slot per stream. A slot holds one batch at a time: its points (8 B each),
+ * offsets, hull indices, counts and workspace. A request is admitted to a
+ * batch only when the batch still fits its slot, so the arena size is the
+ * admission budget and the server never allocates device memory.
+ */
+typedef struct {
+  void* d_arena;             /* device memory, 256-byte aligned, owned by the caller */
+  size_t arena_bytes;        /* admission budget (the whole arena)                   */
+  uint32_t max_inflight;     /* requests submitted and not yet collected by          */
+                             /* ch_serve_wait; 0 means 65536                         */
+  int n_streams;             /* worker streams and arena slots, 1..16; 0 means 4     */
+  uint64_t max_batch_points; /* points per batch at most; 0 means no cap beyond      */
+                             /* what a slot holds                                    */
+} ch_serve_config;
+
+typedef struct ch_server ch_server;
+
+/* Largest request (points) a server with this configuration admits, or 0
+ * when the configuration is invalid. */
+uint64_t ch_serve_max_request_points(const ch_serve_config* cfg);
+
+/* Start a server on the context's device: one worker thread, stream and
+ * library context per slot, plus pinned host staging (allocated here).
+ * `ctx` is only read (device) and may be used or destroyed afterwards.
+ * Errors: CH_E_INVALID_ARG (NULL pointers, misaligned or too small arena,
+ * n_streams out of range), CH_E_NOMEM, CH_E_DEVICE. */
+ch_status ch_serve_start(ch_ctx* ctx, const ch_serve_config* cfg, ch_server** out);
+
+/* Queue one request: n points at h_xy (host memory; pinned memory is copied
+ * by DMA directly, pageable memory through the HIP runtime). The buffer stays
+ * owned by the caller and must stay unchanged until ch_serve_wait has returned
+ * a final status for the ticket. Thread-safe.
+ * Errors: CH_E_BUSY (max_inflight requests outstanding: retry after a wait),
+ * CH_E_INVALID_ARG (NULL pointers, or n above ch_serve_max_request_points),
+ * CH_E_SHUTDOWN (stop has begun). */
+ch_status ch_serve_submit(ch_server* srv, const float* h_xy, uint32_t n, uint64_t* ticket);
+
+/* Wait for a ticket. timeout_us < 0 waits without limit, 0 polls.
+ * On CH_OK the hull (h_out entries, local indices) is in hull_idx and the
+ * ticket is released. t_ns (nullable) receives steady-clock nanoseconds
+ * (CLOCK_MONOTONIC) of arrival (submit), admission (batch start) and
+ * completion. Thread-safe; one waiter per ticket.
+ * Final statuses (ticket released): CH_OK, CH_E_DOMAIN (the set has a domain
+ * error), CH_E_SHUTDOWN (stopped before admission), CH_E_DEVICE.
+ * Non-final (ticket kept): CH_E_TIMEOUT; CH_E_CAPACITY (*h_out = h, hull_idx
+ * untouched: call again with a larger buffer). CH_E_NOT_FOUND: unknown or
+ * already released ticket. */
+ch_status ch_serve_wait(ch_server* srv, uint64_t ticket, int64_t timeout_us, uint32_t* hull_idx,
+                        uint32_t cap, uint32_t* h_out, uint64_t* t_ns);
+
+/* Counters since start: completed requests, batches run, requests per
+ * second over the span from the first arrival to the last completion, and
+ * the 50th / 99th percentile of completion - arrival in microseconds over all
+ * completed requests. Any output pointer may be NULL. Thread-safe. */
+ch_status ch_serve_stats(ch_server* srv, uint64_t* completed, uint64_t* batches,
+                         double* hulls_per_s, double* p50_us, double* p99_us);
+
+/* Stop: refuse new submissions, finish every admitted batch, resolve queued
+ * requests that were never admitted with CH_E_SHUTDOWN, wake blocked waiters
+ * (they return their ticket's final status), then free the server. No call on
+ * `srv` may start once stop has been called. */
+ch_status ch_serve_stop(ch_server* srv);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around each
  * kernel. While enabled, every ch_* call synchronises its stream before
  * returning. ch_profile_read fills up to cap records and returns the number

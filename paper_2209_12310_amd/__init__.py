@@ -9,6 +9,7 @@ library. It never computes any part of the hull itself.
 from __future__ import annotations
 
 import ctypes
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -16,7 +17,7 @@ import numpy as np
 from . import _capi
 from ._capi import CH_COUNT_DOMAIN_ERROR, KernelStat, Octagon, load
 
-__all__ = ["Context", "ConvexHullError", "DomainError", "CapacityError", "FilterResult",
+__all__ = ["Context", "ConvexHullError", "DomainError", "CapacityError", "FilterResult", "Server",
            "default_context", "filter", "hull", "load"]
 
 
@@ -31,6 +32,14 @@ class DomainError(ConvexHullError, ValueError):
 
 
 class CapacityError(ConvexHullError):
+    pass
+
+
+class BusyError(ConvexHullError):
+    pass
+
+
+class WaitTimeout(ConvexHullError):
     pass
 
 
@@ -188,6 +197,11 @@ class Context:
         self.hull_batch_async(xy, off, idx, cnt)
         return idx.cpu().numpy().view(np.uint32)[:n], cnt.cpu().numpy().view(np.uint32)[:nsets]
 
+    def serve(self, arena, n_streams: int = 4, max_inflight: int = 0,
+              max_batch_points: int = 0) -> "Server":
+        """Start a request server on this context's device (ch_serve_start)."""
+        return Server(self, arena, n_streams, max_inflight, max_batch_points)
+
     # -- profiling --------------------------------------------------------
     def profile_enable(self, on: bool = True):
         self._lib.ch_profile_enable(self._h, 1 if on else 0)
@@ -201,6 +215,109 @@ class Context:
         self._lib.ch_profile_read(self._h, ctypes.cast(arr, ctypes.c_void_p), 64, ctypes.byref(n))
         return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
                 for i in range(min(n.value, 64))}
+
+
+def _host_points(xy):
+    """(pointer, n, keep-alive object) for a host float32 (n, 2) array: a
+    numpy array or a CPU torch tensor (pinned memory is copied by DMA)."""
+    if isinstance(xy, np.ndarray):
+        if xy.dtype != np.float32 or xy.ndim != 2 or xy.shape[1] != 2 or not xy.flags.c_contiguous:
+            raise TypeError("points must be a C-contiguous float32 array of shape (n, 2)")
+        return xy.ctypes.data, xy.shape[0], xy
+    torch = _torch()
+    if isinstance(xy, torch.Tensor):
+        if xy.is_cuda:
+            raise TypeError("serve requests are host arrays")
+        if xy.dtype != torch.float32 or xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+            raise TypeError("points must be a contiguous float32 tensor of shape (n, 2)")
+        return xy.data_ptr(), xy.shape[0], xy
+    raise TypeError("points must be a numpy array or a CPU torch tensor")
+
+
+class Server:
+    """A running ch_serve server: submit host point sets, wait for their hulls.
+
+    The arena (a device uint8 tensor) is the admission budget; the server
+    splits it into one slot per stream and never allocates device memory.
+    Submitted arrays are kept referenced until their ticket is collected."""
+
+    def __init__(self, ctx: Context, arena, n_streams: int = 4, max_inflight: int = 0,
+                 max_batch_points: int = 0):
+        torch = _torch()
+        if not isinstance(arena, torch.Tensor) or not arena.is_cuda or arena.dtype != torch.uint8:
+            raise TypeError("arena must be a CUDA uint8 tensor")
+        self._lib = ctx._lib
+        self._ctx = ctx
+        self._arena = arena
+        self._cfg = _capi.ServeConfig(arena.data_ptr(), arena.numel(), max_inflight, n_streams,
+                                      max_batch_points)
+        h = ctypes.c_void_p()
+        st = self._lib.ch_serve_start(ctx._h, ctypes.byref(self._cfg), ctypes.byref(h))
+        if st != _capi.CH_OK:
+            raise ConvexHullError(st, "ch_serve_start failed")
+        self._h = h
+        self._keep = {}
+        self._mu = threading.Lock()
+
+    @property
+    def max_request_points(self) -> int:
+        return int(self._lib.ch_serve_max_request_points(ctypes.byref(self._cfg)))
+
+    def submit(self, xy) -> int:
+        """Queue one request; returns its ticket. Raises BusyError when
+        max_inflight requests are outstanding."""
+        ptr, n, keep = _host_points(xy)
+        t = ctypes.c_uint64(0)
+        st = self._lib.ch_serve_submit(self._h, ctypes.c_void_p(ptr), n, ctypes.byref(t))
+        if st == _capi.CH_E_BUSY:
+            raise BusyError(st, "too many requests in flight")
+        if st != _capi.CH_OK:
+            raise ConvexHullError(st, "ch_serve_submit failed")
+        with self._mu:
+            self._keep[t.value] = (keep, n)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """(hull indices uint32, [arrive, admit, done] ns) of a ticket.
+        Raises WaitTimeout (ticket kept), DomainError, or ConvexHullError."""
+        with self._mu:
+            n = self._keep[ticket][1] if ticket in self._keep else 0
+        cap = max(min(n, 1 << 21), 1)
+        out = np.empty(cap, np.uint32)
+        h = ctypes.c_uint32(0)
+        tns = np.zeros(3, np.uint64)
+        st = self._lib.ch_serve_wait(self._h, ticket, timeout_us, out.ctypes.data_as(ctypes.c_void_p), cap,
+                                     ctypes.byref(h), tns.ctypes.data_as(ctypes.c_void_p))
+        if st == _capi.CH_E_TIMEOUT:
+            raise WaitTimeout(st, f"ticket {ticket} not done")
+        if st not in (_capi.CH_E_NOT_FOUND, _capi.CH_E_CAPACITY):
+            with self._mu:
+                self._keep.pop(ticket, None)
+        if st == _capi.CH_E_DOMAIN:
+            raise DomainError(st, f"ticket {ticket}: input outside the 2^-20 grid on [0,1)")
+        if st != _capi.CH_OK:
+            raise ConvexHullError(st, f"ticket {ticket}")
+        return out[: h.value].copy(), tns
+
+    def stats(self) -> dict:
+        c, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        r, p50, p99 = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        self._lib.ch_serve_stats(self._h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(r),
+                                 ctypes.byref(p50), ctypes.byref(p99))
+        return {"completed": c.value, "batches": b.value, "hulls_per_s": r.value,
+                "p50_us": p50.value, "p99_us": p99.value}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            self._lib.ch_serve_stop(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 _default = None

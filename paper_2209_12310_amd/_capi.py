@@ -42,6 +42,12 @@ class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("max_inflight", ctypes.c_uint32), ("n_streams", ctypes.c_int),
+                ("max_batch_points", ctypes.c_uint64)]
+
+
 # (name, restype, argtypes) for every entry point declared in include/convhull.h.
 P = ctypes.c_void_p
 U32 = ctypes.c_uint32
@@ -59,6 +65,13 @@ SIGNATURES = {
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
     "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),
     "ch_hull_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P]),
+    "ch_serve_max_request_points": (U64, [ctypes.POINTER(ServeConfig)]),
+    "ch_serve_start": (I32, [P, ctypes.POINTER(ServeConfig), ctypes.POINTER(P)]),
+    "ch_serve_submit": (I32, [P, P, U32, ctypes.POINTER(U64)]),
+    "ch_serve_wait": (I32, [P, U64, ctypes.c_int64, P, U32, ctypes.POINTER(U32), P]),
+    "ch_serve_stats": (I32, [P, ctypes.POINTER(U64), ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "ch_serve_stop": (I32, [P]),
     "ch_profile_enable": (I32, [P, I32]),
     "ch_profile_reset": (I32, [P]),
     "ch_profile_read": (I32, [P, P, I32, ctypes.POINTER(I32)]),

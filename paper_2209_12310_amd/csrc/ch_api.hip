@@ -81,6 +81,10 @@ struct ch_ctx {
   std::vector<hipEvent_t> pool;
 };
 
+namespace chk {
+int ctx_device(const ch_ctx* ctx) { return ctx->device; }
+}  // namespace chk
+
 namespace {
 
 struct DeviceGuard {

@@ -78,3 +78,37 @@ def test_binding_rejects_host_tensors():
     import paper_2209_12310_amd as ch
     with pytest.raises(TypeError):
         ch._check_points(torch.zeros((4, 2), dtype=torch.float32))
+
+
+def test_serve_admission_limits(lib):
+    """ch_serve_max_request_points is pure host arithmetic over the slot
+    layout: it grows with the arena, shrinks with more streams, and rejects
+    configurations outside the documented ranges."""
+    f = lib.ch_serve_max_request_points
+    f.restype = ctypes.c_uint64
+    f.argtypes = [ctypes.POINTER(_capi.ServeConfig)]
+
+    def m(arena, streams, cap=0):
+        return f(ctypes.byref(_capi.ServeConfig(256, arena, 0, streams, cap)))
+
+    assert m(64 << 30, 4) > m(8 << 30, 4) > m(1 << 30, 4) > 0
+    assert m(8 << 30, 1) > m(8 << 30, 8)
+    assert m(1 << 30, 0) == m(1 << 30, 4)  # 0 streams means the default 4
+    assert m(1 << 30, 17) == 0 and m(1 << 30, -1) == 0
+    assert m(4096, 1) == 0  # too small for any request
+    assert m(8 << 30, 2, 12345) == 12345
+    # 10^7-point requests (the largest in the serving trace) fit a 16 GB slot.
+    assert m(64 << 30, 4) >= 10**7
+
+
+def test_serve_null_arguments(lib):
+    lib.ch_serve_start.restype = ctypes.c_int
+    lib.ch_serve_submit.restype = ctypes.c_int
+    lib.ch_serve_stats.restype = ctypes.c_int
+    lib.ch_serve_stop.restype = ctypes.c_int
+    out = ctypes.c_void_p()
+    assert lib.ch_serve_start(None, None, ctypes.byref(out)) == 1
+    t = ctypes.c_uint64()
+    assert lib.ch_serve_submit(None, None, 0, ctypes.byref(t)) == 1
+    assert lib.ch_serve_stats(None, None, None, None, None, None) == 1
+    assert lib.ch_serve_stop(None) == 1
