@@ -63,19 +63,62 @@ def load_traffic(n: int, kernel: str):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(xy, budget_s: float = 12.0):
-    """The CPU oracle as it stands (single thread), timed on the host."""
+def cpu_baseline(xy, budget_s: float = 8.0):
+    """The CPU oracle as it stands, timed on the host: the multi-core variant
+    (grid conversion, the OpenMP divide-and-conquer octagon filter on every
+    host thread, monotone chain of the survivors) and the single-thread
+    heaphull, each on the full headline input within a time budget."""
     import oracle
+
+    def timed(fn):
+        reps, total = 0, 0.0
+        while reps < 5 and (reps == 0 or total < budget_s):
+            t0 = time.perf_counter()
+            fn()
+            total += time.perf_counter() - t0
+            reps += 1
+        return reps, total
+
+    def multi():
+        kx, ky = oracle.to_grid(xy)
+        _, surv = oracle.filter_parallel(kx, ky)
+        return oracle.chain(kx, ky, surv)
+
     n = xy.shape[0]
-    reps, total = 0, 0.0
-    while reps < 5 and (reps == 0 or total < budget_s):
-        t0 = time.perf_counter()
-        oracle.hull(xy)
-        total += time.perf_counter() - t0
-        reps += 1
-    return {"value": round(n * reps / total / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {WORKLOAD} input ({n} points), {reps} run(s), {total:.1f} s total, "
-                      f"to_grid + extremes + octagon filter + monotone chain"}
+    cores = oracle.max_threads()
+    reps, total = timed(multi)
+    reps1, total1 = timed(lambda: oracle.hull(xy))
+    return {"value": round(n * reps / total / 1e6, 3), "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"full {WORKLOAD} input ({n} points), {reps} run(s) in {total:.1f} s: grid "
+                      f"conversion, octagon filter on {cores} threads (divide and conquer), monotone chain",
+            "single_thread_value": round(n * reps1 / total1 / 1e6, 3),
+            "single_thread_sample": f"{reps1} run(s) in {total1:.1f} s of the sequential heaphull"}
+
+
+def bench_single(ctx, name: str, steps: int, warmup: int) -> dict:
+    """ch_hull end to end on one more single-set configuration."""
+    import torch
+
+    from paper_2209_12310_amd import workloads
+    log(f"generating {name}")
+    xy = workloads.single(name)
+    n = xy.shape[0]
+    t = torch.from_numpy(xy).to("cuda:0")
+    for _ in range(warmup):
+        hull = ctx.hull(t)
+    fr = ctx.filter(t)
+    survivors = fr.count
+    del fr
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hull = ctx.hull(t)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    del t
+    return {"workload": name, "n": n, "ms_per_step": round(ms, 4), "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+            "hbm_frac_16B_per_pt": round(16 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "octagon_survivors": survivors, "h": int(hull.size)}
 
 
 def pct(vals, q):
@@ -85,9 +128,10 @@ def pct(vals, q):
 
 def bench_batch(ctx, steps: int, warmup: int) -> dict:
     """Batched mode on 4096 sets (log-uniform sizes in [1e3, 1e6], kinds
-    uniform / normal / annulus 0.49-0.5, seed 3): one ch_hull_batch call per
-    step, timed with events on the launch stream; compared with one ch_hull
-    call per set on the same device-resident points."""
+    uniform / normal / annulus 0.49-0.5, seed 3): parameters from the
+    autotuner, then one ch_hull_batch call per step, timed with events on the
+    launch stream; compared with one ch_hull call per set on the same
+    device-resident points."""
     import numpy as np
     import torch
 
@@ -101,6 +145,10 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
     idx = torch.empty(n, dtype=torch.int32, device="cuda:0")
     cnt = torch.empty(nsets, dtype=torch.int32, device="cuda:0")
     ws = ctx.workspace(ctx._lib.ch_hull_batch_workspace_bytes(nsets, n))
+    log("tuning batch parameters")
+    t0 = time.perf_counter()
+    params = ctx.tune_batch(t, o, idx, cnt, ws)
+    tune_s = time.perf_counter() - t0
     for _ in range(warmup):
         ctx.hull_batch_async(t, o, idx, cnt, ws)
     torch.cuda.synchronize()
@@ -135,6 +183,7 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
             "batch_p50_ms": round(pct(lat, 50), 3), "batch_p99_ms": round(pct(lat, 99), 3),
             "plain_ms": round(plain * 1e3, 1), "plain_hulls_per_s": round(nsets / plain, 1),
             "speedup_vs_plain": round(plain / (ms * 1e-3), 2),
+            "params": params, "tune_s": round(tune_s, 2),
             "kinds": {k: kinds.count(k) for k in sorted(set(kinds))}}
 
 
@@ -251,6 +300,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other single-set configurations")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -345,6 +395,14 @@ def main() -> int:
     }
     del t
     torch.cuda.synchronize()
+    out["single_sets"] = {WORKLOAD: {"workload": WORKLOAD, "n": n, "ms_per_step": round(ms, 4),
+                                     "mpts_per_s": round(value, 1),
+                                     "hbm_frac_16B_per_pt": out["hbm_frac_end_to_end"],
+                                     "octagon_survivors": survivors, "h": int(hull.size)}}
+    if not args.no_extra:
+        for name in ("uniform_1e6", "annulus_1e8"):
+            out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 2)
+            torch.cuda.synchronize()
     if not args.no_batch:
         out["batch"] = bench_batch(ctx, max(5, min(args.steps, 20)), 1)
         torch.cuda.synchronize()

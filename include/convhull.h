@@ -77,8 +77,10 @@ typedef struct {
   uint32_t idx[8];
 } ch_octagon;
 
-/* Create a context bound to HIP device `hip_device`. tune_cache_path may be
- * NULL. Allocates pinned host staging memory and nothing on the device.
+/* Create a context bound to HIP device `hip_device`. tune_cache_path (may be
+ * NULL) names a text file of batch tuning results (see ch_tune_batch); it is
+ * read here if it exists. Allocates pinned host staging memory and nothing
+ * on the device.
  * Errors: CH_E_INVALID_ARG (out is NULL), CH_E_DEVICE, CH_E_NOMEM. */
 ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** out);
 /* Destroy a context (NULL is ignored). Waits for nothing: the caller must
@@ -159,6 +161,45 @@ size_t ch_hull_batch_workspace_bytes(uint32_t nsets, uint64_t total_points);
 ch_status ch_hull_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
                         uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
                         void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batch-mode launch parameters (not in the paper; they change speed, never
+ * results). tile_points: points per pass tile of a set (power of two, 4096 ..
+ * 65536); pass_blocks / hull_blocks: workgroups of the persistent filter
+ * grid and of the per-set hull kernels (1 .. 65535); sample_min: sets of at
+ * least this many points (and at least 2048) get a refined filter polygon
+ * from a sample of their points (0xFFFFFFFF: none).
+ */
+typedef struct {
+  uint32_t tile_points;
+  uint32_t pass_blocks;
+  uint32_t hull_blocks;
+  uint32_t sample_min;
+} ch_batch_params;
+
+/* The parameters ch_hull_batch would use for nsets sets of total_points
+ * points: those set with ch_batch_params_set, else the tuned entry (this
+ * context's tuning or the tune cache) nearest in log2 of both sizes, else
+ * the defaults. */
+ch_status ch_batch_params_get(const ch_ctx* ctx, uint32_t nsets, uint64_t total_points,
+                              ch_batch_params* out);
+/* Fix the parameters for every later call (NULL: back to tuned/defaults).
+ * CH_E_INVALID_ARG when out of range. */
+ch_status ch_batch_params_set(ch_ctx* ctx, const ch_batch_params* p);
+
+/*
+ * ch_tune_batch -- autotuner: runs ch_hull_batch on the given batch with
+ * candidate parameters (coordinate descent over tile size, pass grid, hull
+ * grid and sample threshold, median of three timed runs each), keeps the
+ * fastest for batches of this shape (log2 of nsets and total_points), and,
+ * when the context was created with a tune_cache_path, rewrites that file
+ * with this device's entries (ch_ctx_create loads it). Synchronous; the
+ * arguments are those of ch_hull_batch, whose outputs hold the batch's
+ * result on return. best_out may be NULL.
+ */
+ch_status ch_tune_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
+                        uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
+                        void* d_ws, size_t ws_bytes, void* stream, ch_batch_params* best_out);
 
 /*
  * Serving: a request is one point set in host memory; the server copies it to

@@ -73,11 +73,11 @@ class FilterResult:
 class Context:
     """A library context bound to one HIP device, with a cached workspace."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache: str | None = None):
         self._lib = load()
         self.device = device
         h = ctypes.c_void_p()
-        st = self._lib.ch_ctx_create(device, None, ctypes.byref(h))
+        st = self._lib.ch_ctx_create(device, tune_cache.encode() if tune_cache else None, ctypes.byref(h))
         if st != _capi.CH_OK:
             raise ConvexHullError(st, "ch_ctx_create failed")
         self._h = h
@@ -196,6 +196,49 @@ class Context:
         cnt = torch.empty(max(nsets, 1), dtype=torch.int32, device=xy.device)
         self.hull_batch_async(xy, off, idx, cnt)
         return idx.cpu().numpy().view(np.uint32)[:n], cnt.cpu().numpy().view(np.uint32)[:nsets]
+
+    @staticmethod
+    def _params_dict(p) -> dict:
+        return {"tile_points": p.tile_points, "pass_blocks": p.pass_blocks,
+                "hull_blocks": p.hull_blocks, "sample_min": p.sample_min}
+
+    def batch_params(self, nsets: int = 1, total_points: int = 1) -> dict:
+        """The batch parameters a call of this shape would use."""
+        p = _capi.BatchParams()
+        st = self._lib.ch_batch_params_get(self._h, nsets, total_points, ctypes.byref(p))
+        if st != _capi.CH_OK:
+            self._raise(st)
+        return self._params_dict(p)
+
+    def set_batch_params(self, params: dict | None):
+        """Fix the batch parameters (None: back to tuned / default ones)."""
+        if params is None:
+            st = self._lib.ch_batch_params_set(self._h, None)
+        else:
+            p = _capi.BatchParams(params["tile_points"], params["pass_blocks"], params["hull_blocks"],
+                                  params["sample_min"])
+            st = self._lib.ch_batch_params_set(self._h, ctypes.byref(p))
+        if st != _capi.CH_OK:
+            self._raise(st)
+
+    def tune_batch(self, xy, off, hull_idx, hull_count, ws=None) -> dict:
+        """ch_tune_batch on device tensors (as hull_batch_async); returns the
+        chosen parameters. Synchronous."""
+        torch = _torch()
+        n = _check_points(xy)
+        if off.dtype != torch.int64 or not off.is_cuda or off.dim() != 1:
+            raise TypeError("offsets must be a 1-D int64 CUDA tensor")
+        nsets = off.numel() - 1
+        if ws is None:
+            ws = self.workspace(self._lib.ch_hull_batch_workspace_bytes(nsets, n))
+        best = _capi.BatchParams()
+        st = self._lib.ch_tune_batch(
+            self._h, ctypes.c_void_p(xy.data_ptr()), ctypes.c_void_p(off.data_ptr()), nsets, n,
+            ctypes.c_void_p(hull_idx.data_ptr()), ctypes.c_void_p(hull_count.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), self.stream_handle(), ctypes.byref(best))
+        if st != _capi.CH_OK:
+            self._raise(st)
+        return self._params_dict(best)
 
     def serve(self, arena, n_streams: int = 4, max_inflight: int = 0,
               max_batch_points: int = 0) -> "Server":

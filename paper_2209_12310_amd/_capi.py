@@ -42,6 +42,11 @@ class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class BatchParams(ctypes.Structure):
+    _fields_ = [("tile_points", ctypes.c_uint32), ("pass_blocks", ctypes.c_uint32),
+                ("hull_blocks", ctypes.c_uint32), ("sample_min", ctypes.c_uint32)]
+
+
 class ServeConfig(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_uint32), ("n_streams", ctypes.c_int),
@@ -65,6 +70,9 @@ SIGNATURES = {
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
     "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),
     "ch_hull_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P]),
+    "ch_batch_params_get": (I32, [P, U32, U64, ctypes.POINTER(BatchParams)]),
+    "ch_batch_params_set": (I32, [P, ctypes.POINTER(BatchParams)]),
+    "ch_tune_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P, ctypes.POINTER(BatchParams)]),
     "ch_serve_max_request_points": (U64, [ctypes.POINTER(ServeConfig)]),
     "ch_serve_start": (I32, [P, ctypes.POINTER(ServeConfig), ctypes.POINTER(P)]),
     "ch_serve_submit": (I32, [P, P, U32, ctypes.POINTER(U64)]),

@@ -2,11 +2,15 @@
 // workspace layout, kernel sequencing, result staging and profiling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -18,9 +22,11 @@ hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);
 uint32_t reduce_blocks(uint32_t n, uint32_t max_blocks);
 uint32_t filter_blocks(uint32_t n, uint32_t max_blocks);
 hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
-                          uint32_t* part_bad, uint32_t blocks, hipStream_t st);
+                          uint32_t* part_bad, void* sample_scratch, uint32_t blocks,
+                          hipStream_t st);
 hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
+                            const float* xy, uint32_t n, void* sample_scratch, SamplePoly* poly,
                             hipStream_t st);
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
                          uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
@@ -28,7 +34,7 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             Rec* staging, hipStream_t st);
+                             Rec* staging, const SamplePoly* poly, hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -44,8 +50,10 @@ hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl
 hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
                               Result* res, uint32_t* res_idx, hipStream_t st);
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
-                                    uint64_t total_points, BatchHdr* bh, SetState* sets,
-                                    SetTile* tiles, Rec* recs, uint32_t grid, hipStream_t st);
+                                    uint64_t total_points, uint32_t tile, BatchHdr* bh,
+                                    SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
+                                    uint32_t grid, uint32_t sample_min, uint32_t sample_grid,
+                                    hipStream_t st);
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
@@ -74,6 +82,14 @@ struct ch_ctx {
   uint32_t filter_max_blocks = 1024;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   std::string err;
+  // Batch-mode parameters: fixed ones (ch_batch_params_set), else the tuned
+  // entry nearest to the call's shape, else the defaults.
+  ch_batch_params batch{};
+  bool batch_fixed = false;
+  struct TuneEntry { int lg_sets, lg_points; ch_batch_params p; };
+  std::vector<TuneEntry> tuned;
+  std::string arch;
+  std::string tune_path;
   bool prof = false;
   std::vector<KStat> stats;
   struct Pending { int stat; hipEvent_t a, b; };
@@ -176,9 +192,14 @@ T* at(void* ws, size_t off) {
 }
 
 // Enqueues pass 1 (reduce + octagon build) and pass 2 (filter + compaction).
+// With surv_rec (the hull path) the survivors are records, and for n >=
+// kSampleMin the octagon build also builds the refined filter's polygon.
 ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
                      uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
                      hipStream_t st, Rec* surv_rec = nullptr, Rec* rec_staging = nullptr) {
+  const bool sample = surv_rec && n >= kSampleMin;
+  SamplePoly* poly = sample ? at<SamplePoly>(ws, L.poly) : nullptr;
+  void* scratch = sample ? at<void>(ws, L.samp) : nullptr;
   const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
   Header* hdr = at<Header>(ws, L.hdr);
   Result* res = at<Result>(ws, L.res);
@@ -187,21 +208,21 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
   hipError_t e;
   {
     ProfScope p(ctx, st, "reduce8");
-    e = launch_reduce8(d_xy, n, head, at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad), g1,
-                       st);
+    e = launch_reduce8(d_xy, n, head, at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad),
+                       scratch, g1, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
   {
     ProfScope p(ctx, st, "oct_build");
     e = launch_oct_build(at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad), g1, hdr, res,
-                         at<uint64_t>(ws, L.tstat), g2, st);
+                         at<uint64_t>(ws, L.tstat), g2, d_xy, n, scratch, poly, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
   {
     ProfScope p(ctx, st, "filter_compact");
     if (surv_rec)
       e = launch_filter_rec(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv_rec, count_out,
-                            rec_staging, st);
+                            rec_staging, poly, st);
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);
@@ -215,6 +236,127 @@ ch_status check_points(ch_ctx* ctx, const float* d_xy, uint32_t n) {
   if (n && !d_xy) return fail(ctx, CH_E_INVALID_ARG, "d_xy is NULL");
   if (reinterpret_cast<uintptr_t>(d_xy) & 7u)
     return fail(ctx, CH_E_INVALID_ARG, "d_xy must be 8-byte aligned");
+  return CH_OK;
+}
+
+ch_batch_params default_batch_params(int cu) {
+  ch_batch_params p;
+  p.tile_points = kBatchTile;
+  p.pass_blocks = (uint32_t)cu * 4;
+  p.hull_blocks = (uint32_t)cu * 3;
+  p.sample_min = kBatchSampleMin;
+  return p;
+}
+
+bool valid_batch_params(const ch_batch_params& p) {
+  const uint32_t t = p.tile_points;
+  return t >= kBatchTileMin && t <= kBatchTileMax && (t & (t - 1)) == 0 && p.pass_blocks >= 1 &&
+         p.pass_blocks <= 65535 && p.hull_blocks >= 1 && p.hull_blocks <= 65535;
+}
+
+int lg_bucket(uint64_t v) { return v ? 63 - __builtin_clzll(v) : -1; }
+
+// Tune cache: text lines "convhull-tune 1 <arch> <cu> <lg_sets> <lg_points>
+// <tile> <pass> <hull> <sample_min>"; lines for other devices are kept.
+void load_tune_cache(ch_ctx* ctx) {
+  std::ifstream f(ctx->tune_path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string tag, arch;
+    int ver = 0, cu = 0;
+    ch_ctx::TuneEntry e{};
+    if (!(in >> tag >> ver >> arch >> cu >> e.lg_sets >> e.lg_points >> e.p.tile_points >>
+          e.p.pass_blocks >> e.p.hull_blocks >> e.p.sample_min))
+      continue;
+    if (tag != "convhull-tune" || ver != 1 || arch != ctx->arch || cu != ctx->cu_count) continue;
+    if (!valid_batch_params(e.p)) continue;
+    ctx->tuned.push_back(e);
+  }
+}
+
+bool save_tune_cache(const ch_ctx* ctx) {
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(ctx->tune_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream in(line);
+      std::string tag, arch;
+      int ver = 0, cu = 0;
+      if ((in >> tag >> ver >> arch >> cu) && tag == "convhull-tune" && arch == ctx->arch &&
+          cu == ctx->cu_count)
+        continue;  // rewritten below
+      if (!line.empty()) keep.push_back(line);
+    }
+  }
+  const std::string tmp = ctx->tune_path + ".tmp";
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    if (!o) return false;
+    for (const auto& l : keep) o << l << "\n";
+    for (const auto& e : ctx->tuned)
+      o << "convhull-tune 1 " << ctx->arch << ' ' << ctx->cu_count << ' ' << e.lg_sets << ' '
+        << e.lg_points << ' ' << e.p.tile_points << ' ' << e.p.pass_blocks << ' ' << e.p.hull_blocks
+        << ' ' << e.p.sample_min << "\n";
+    if (!o) return false;
+  }
+  return std::rename(tmp.c_str(), ctx->tune_path.c_str()) == 0;
+}
+
+ch_batch_params batch_params_for(const ch_ctx* ctx, uint32_t nsets, uint64_t total) {
+  if (ctx->batch_fixed || ctx->tuned.empty()) return ctx->batch;
+  const int ls = lg_bucket(nsets), lp = lg_bucket(total);
+  const ch_ctx::TuneEntry* best = nullptr;
+  int bd = 1 << 30;
+  for (const auto& e : ctx->tuned) {
+    const int d = std::abs(e.lg_sets - ls) + std::abs(e.lg_points - lp);
+    if (d < bd) { bd = d; best = &e; }
+  }
+  return best->p;
+}
+
+ch_status check_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
+                      uint64_t total_points, const uint32_t* d_hull_idx,
+                      const uint32_t* d_hull_count, void* d_ws, size_t ws_bytes) {
+  if (!d_off || !d_hull_count) return fail(ctx, CH_E_INVALID_ARG, "d_off / d_hull_count is NULL");
+  if (total_points >= 0xFFFFFFFFull)
+    return fail(ctx, CH_E_INVALID_ARG, "total_points must stay below 2^32");
+  if (total_points && (!d_xy || !d_hull_idx))
+    return fail(ctx, CH_E_INVALID_ARG, "d_xy / d_hull_idx is NULL");
+  if (reinterpret_cast<uintptr_t>(d_xy) & 15u)
+    return fail(ctx, CH_E_INVALID_ARG, "d_xy must be 16-byte aligned in batch mode");
+  const size_t need = batch_layout(nsets, total_points).total;
+  if (!d_ws || ws_bytes < need)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  return CH_OK;
+}
+
+// Enqueues one batch with parameters p (arguments already checked).
+ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
+                    const uint64_t* d_off, uint32_t nsets, uint64_t total_points,
+                    uint32_t* d_hull_idx, uint32_t* d_hull_count, void* d_ws, hipStream_t st) {
+  const BatchLayout L = batch_layout(nsets, total_points);
+  BatchHdr* bh = at<BatchHdr>(d_ws, L.hdr);
+  SetState* sets = at<SetState>(d_ws, L.sets);
+  Rec* recA = at<Rec>(d_ws, L.recA);
+  Rec* recB = at<Rec>(d_ws, L.recB);
+  hipError_t e;
+  {
+    ProfScope ps(ctx, st, "batch_filter");
+    e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
+                                 at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles), recA,
+                                 p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 2, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
+  {
+    ProfScope ps(ctx, st, "batch_hull");
+    e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
+                               d_hull_idx, d_hull_count, p.hull_blocks, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch hull launch");
   return CH_OK;
 }
 
@@ -240,7 +382,6 @@ const char* ch_status_string(ch_status s) {
 }
 
 ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** out) {
-  (void)tune_cache_path;
   if (!out) return CH_E_INVALID_ARG;
   *out = nullptr;
   int ndev = 0;
@@ -271,6 +412,18 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
                     hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return CH_E_NOMEM;
+  }
+  ctx->batch = default_batch_params(ctx->cu_count);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->arch = prop.gcnArchName;
+    const size_t colon = ctx->arch.find(':');
+    if (colon != std::string::npos) ctx->arch.resize(colon);
+    if (ctx->arch.empty()) ctx->arch = "unknown";
+  }
+  if (tune_cache_path && *tune_cache_path) {
+    ctx->tune_path = tune_cache_path;
+    load_tune_cache(ctx);
   }
   *out = ctx;
   return CH_OK;
@@ -480,39 +633,114 @@ ch_status ch_hull_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, u
                         void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx) return CH_E_INVALID_ARG;
   if (nsets == 0) return CH_OK;
-  if (!d_off || !d_hull_count) return fail(ctx, CH_E_INVALID_ARG, "d_off / d_hull_count is NULL");
-  if (total_points >= 0xFFFFFFFFull)
-    return fail(ctx, CH_E_INVALID_ARG, "total_points must stay below 2^32");
-  if (total_points && (!d_xy || !d_hull_idx))
-    return fail(ctx, CH_E_INVALID_ARG, "d_xy / d_hull_idx is NULL");
-  if (reinterpret_cast<uintptr_t>(d_xy) & 15u)
-    return fail(ctx, CH_E_INVALID_ARG, "d_xy must be 16-byte aligned in batch mode");
-  const BatchLayout L = batch_layout(nsets, total_points);
-  if (!d_ws || ws_bytes < L.total)
-    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
-  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
-    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ch_status s = check_batch(ctx, d_xy, d_off, nsets, total_points, d_hull_idx, d_hull_count,
+                                d_ws, ws_bytes))
+    return s;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  BatchHdr* bh = at<BatchHdr>(d_ws, L.hdr);
-  SetState* sets = at<SetState>(d_ws, L.sets);
-  Rec* recA = at<Rec>(d_ws, L.recA);
-  Rec* recB = at<Rec>(d_ws, L.recB);
-  hipError_t e;
-  {
-    ProfScope p(ctx, st, "batch_filter");
-    e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, bh, sets, at<SetTile>(d_ws, L.tiles),
-                                 recA, ctx->filter_max_blocks, st);
-  }
-  if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
-  {
-    ProfScope p(ctx, st, "batch_hull");
-    e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
-                               d_hull_idx, d_hull_count, (uint32_t)ctx->cu_count * 3, st);
-  }
-  if (e != hipSuccess) return hip_fail(ctx, e, "batch hull launch");
+  if (ch_status s = run_batch(ctx, batch_params_for(ctx, nsets, total_points), d_xy, d_off, nsets,
+                              total_points, d_hull_idx, d_hull_count, d_ws, st))
+    return s;
   prof_collect(ctx, st);
+  return CH_OK;
+}
+
+ch_status ch_batch_params_get(const ch_ctx* ctx, uint32_t nsets, uint64_t total_points,
+                              ch_batch_params* out) {
+  if (!ctx || !out) return CH_E_INVALID_ARG;
+  *out = batch_params_for(ctx, nsets, total_points);
+  return CH_OK;
+}
+
+ch_status ch_batch_params_set(ch_ctx* ctx, const ch_batch_params* p) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (!p) {
+    ctx->batch = default_batch_params(ctx->cu_count);
+    ctx->batch_fixed = false;
+    return CH_OK;
+  }
+  if (!valid_batch_params(*p)) return fail(ctx, CH_E_INVALID_ARG, "batch parameters out of range");
+  ctx->batch = *p;
+  ctx->batch_fixed = true;
+  return CH_OK;
+}
+
+ch_status ch_tune_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, uint32_t nsets,
+                        uint64_t total_points, uint32_t* d_hull_idx, uint32_t* d_hull_count,
+                        void* d_ws, size_t ws_bytes, void* stream, ch_batch_params* best_out) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (nsets == 0) return fail(ctx, CH_E_INVALID_ARG, "nothing to tune on");
+  if (ch_status s = check_batch(ctx, d_xy, d_off, nsets, total_points, d_hull_idx, d_hull_count,
+                                d_ws, ws_bytes))
+    return s;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    if (ea) (void)hipEventDestroy(ea);
+    ctx->prof = prof;
+    return fail(ctx, CH_E_DEVICE, "event creation failed");
+  }
+  // Median of three timed runs after one warm-up.
+  auto time_of = [&](const ch_batch_params& p, float& ms) -> ch_status {
+    float t[3];
+    for (int r = -1; r < 3; ++r) {
+      hipError_t e = hipEventRecord(ea, st);
+      if (e != hipSuccess) return hip_fail(ctx, e, "tune event");
+      if (ch_status s = run_batch(ctx, p, d_xy, d_off, nsets, total_points, d_hull_idx,
+                                  d_hull_count, d_ws, st))
+        return s;
+      e = hipEventRecord(eb, st);
+      if (e == hipSuccess) e = hipEventSynchronize(eb);
+      if (e == hipSuccess && r >= 0) e = hipEventElapsedTime(&t[r], ea, eb);
+      if (e != hipSuccess) return hip_fail(ctx, e, "tune timing");
+    }
+    std::sort(t, t + 3);
+    ms = t[1];
+    return CH_OK;
+  };
+  // Coordinate descent from the defaults: tile size, pass grid, hull grid,
+  // then the set size from which sets get a sample polygon.
+  const uint32_t cu = (uint32_t)ctx->cu_count;
+  ch_batch_params best = default_batch_params(ctx->cu_count);
+  float best_ms = 0.f;
+  ch_status st_all = time_of(best, best_ms);
+  const uint32_t tiles[] = {4096, 8192, 16384, 32768};
+  const uint32_t passm[] = {2, 4, 8};
+  const uint32_t hullm[] = {2, 3, 4, 6};
+  const uint32_t smins[] = {1u << 13, 1u << 15, 1u << 17, 0xFFFFFFFFu};
+  for (int dim = 0; dim < 4 && st_all == CH_OK; ++dim) {
+    const int nv = dim == 1 ? 3 : 4;
+    for (int i = 0; i < nv && st_all == CH_OK; ++i) {
+      ch_batch_params c = best;
+      if (dim == 0) c.tile_points = tiles[i];
+      if (dim == 1) c.pass_blocks = passm[i] * cu;
+      if (dim == 2) c.hull_blocks = hullm[i] * cu;
+      if (dim == 3) c.sample_min = smins[i];
+      if (std::memcmp(&c, &best, sizeof c) == 0) continue;
+      float ms = 0.f;
+      st_all = time_of(c, ms);
+      if (st_all == CH_OK && ms < best_ms) { best_ms = ms; best = c; }
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  ctx->prof = prof;
+  if (st_all != CH_OK) return st_all;
+  // The outputs hold the last run's (correct) result; record the winner.
+  const int ls = lg_bucket(nsets), lp = lg_bucket(total_points);
+  bool replaced = false;
+  for (auto& e : ctx->tuned)
+    if (e.lg_sets == ls && e.lg_points == lp) { e.p = best; replaced = true; }
+  if (!replaced) ctx->tuned.push_back({ls, lp, best});
+  ctx->batch_fixed = false;
+  if (best_out) *best_out = best;
+  if (!ctx->tune_path.empty() && !save_tune_cache(ctx))
+    return fail(ctx, CH_E_INVALID_ARG, "cannot write the tune cache %s", ctx->tune_path.c_str());
   return CH_OK;
 }
 

@@ -5,6 +5,8 @@
 
 namespace chk {
 
+static constexpr float kGridF = 1048576.0f;  // 2^20: float units -> grid units
+
 __device__ __forceinline__ double cross3(int32_t ax, int32_t ay, int32_t bx, int32_t by, int32_t cx,
                                          int32_t cy) {
   const double t = (double)(by - ay) * (double)(cx - ax);
@@ -88,6 +90,35 @@ __device__ inline void bitonic_sort(uint64_t* key, uint32_t P2) {
     }
   }
   __syncthreads();
+}
+
+// Sample-polygon tests (see SamplePoly). in_disc: a point of the disc is
+// strictly inside the polygon. dx, dy are exact (both operands are multiples
+// of 2^-20 in [0, 1)); the fp32 sum of squares is at least (1 - 2^-23) times
+// the exact one, and r2 carries a larger margin, so the test never accepts a
+// point outside the exact disc.
+__device__ __forceinline__ bool in_disc(float x, float y, float cx, float cy, float r2) {
+  const float dx = x - cx, dy = y - cy;
+  return __builtin_fmaf(dx, dx, dy * dy) < r2;
+}
+
+// Exact: p strictly inside the counter-clockwise strictly convex polygon
+// v[0..nv) (nv >= 3). p must lie strictly left of v0->v1 and strictly right
+// of v0->v[nv-1]; a binary search over the fan at v0 finds the wedge
+// v0, v_lo, v_lo+1 holding p, and p is inside when strictly left of that
+// wedge's outer side.
+__device__ __forceinline__ bool poly_strict_inside(const int32_t* vx, const int32_t* vy, uint32_t nv,
+                                                   int32_t px, int32_t py) {
+  const int32_t ax = vx[0], ay = vy[0];
+  if (!(cross3(ax, ay, vx[1], vy[1], px, py) > 0.0)) return false;
+  if (!(cross3(ax, ay, vx[nv - 1], vy[nv - 1], px, py) < 0.0)) return false;
+  uint32_t lo = 1, hi = nv - 1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cross3(ax, ay, vx[mid], vy[mid], px, py) >= 0.0) lo = mid;
+    else hi = mid;
+  }
+  return cross3(vx[lo], vy[lo], vx[hi], vy[hi], px, py) > 0.0;
 }
 
 // Block-wide exclusive scan of one value per thread (all threads call it).

@@ -18,7 +18,7 @@
 // All predicates are exact: coordinates are multiples of 2^-20 below 1, so the
 // keys (< 2^45 in units of 2^-20) and the edge forms (< 2^42) are integers that
 // fp64 represents exactly, and every fma below rounds nothing.
-#include "ch_device.hpp"
+#include "ch_refine.hpp"
 
 namespace chk {
 
@@ -31,7 +31,6 @@ __device__ __forceinline__ float4 ld_stream(const float4* p) {
   const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
   return make_float4(v.x, v.y, v.z, v.w);
 }
-static constexpr float kGridF = 1048576.0f;  // 2^20
 
 struct Keys {
   double mxE, mnE, mxN, mnN, mxNE, mnNE, mxSE, mnSE;
@@ -262,7 +261,9 @@ constexpr int kU = 4;
 
 __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
                                                     uint32_t head, double* __restrict__ partials,
-                                                    uint32_t* __restrict__ part_bad) {
+                                                    uint32_t* __restrict__ part_bad,
+                                                    SampleDirs* __restrict__ sd) {
+  if (sd && blockIdx.x == 0) sample_dirs_clear(sd);  // for the octagon build's sample blocks
   Keys k;
   keys_init(k);
   bool bad = false;
@@ -318,15 +319,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy
   }
 }
 
-// One workgroup: combine the pass-1 partials (all loads issued up front),
+// Workgroup 0: combine the pass-1 partials (all loads issued up front),
 // build the octagon, and reset every per-call counter and look-back word used
-// by the kernels that follow.
+// by the kernels that follow. On the hull path (sd != null) workgroups 1 ..
+// kSampleBlocks build the sample polygon of the refined filter meanwhile.
 __global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__ partials,
                                                       const uint32_t* __restrict__ part_bad,
                                                       uint32_t nparts, Header* __restrict__ hdr,
                                                       Result* __restrict__ res,
                                                       uint64_t* __restrict__ tstat,
-                                                      uint32_t ntstat) {
+                                                      uint32_t ntstat,
+                                                      const float* __restrict__ xy, uint32_t n,
+                                                      SampleDirs* __restrict__ sd,
+                                                      SamplePoly* __restrict__ poly) {
+  if (blockIdx.x > 0) {
+    sample_dirs_block(xy, n, sd, poly, blockIdx.x - 1, gridDim.x - 1);
+    return;
+  }
   constexpr int kPer = kReduceMaxBlocks / kBlock;
   Keys k;
   keys_init(k);
@@ -448,6 +457,17 @@ template <class P>
 struct StageCap {
   static constexpr int value = 8192 / (int)sizeof(P);  // 8 KiB of LDS per wave
 };
+// Records leave room for the sample polygon and the exact-test queue within
+// 40 KiB per workgroup (four workgroups per CU).
+template <>
+struct StageCap<Rec> {
+  static constexpr int value = 448;
+};
+
+// Exact-test queue of the hull path: points that pass neither cheap test
+// wait in LDS until a whole wave's worth (64) can be tested together, so the
+// exact tests run with full waves however rare those points are.
+constexpr int kQueue = 128;
 
 template <bool LABELS, class P>
 __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy, uint32_t n,
@@ -456,16 +476,34 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
                                                    P* __restrict__ surv,
                                                    uint32_t* __restrict__ count_out,
                                                    uint8_t* __restrict__ labels,
-                                                   P* __restrict__ staging) {
+                                                   P* __restrict__ staging,
+                                                   const SamplePoly* __restrict__ poly) {
   constexpr int kCapW = StageCap<P>::value;
+  constexpr bool kHull = sizeof(P) == sizeof(Rec);  // hull path: records, queue, sample polygon
+  constexpr int kQ = kHull ? kQueue : 1;
+  constexpr int kPV = kHull ? kPolyMax : 1;
   __shared__ P s_buf[kWaves][kCapW];
   __shared__ uint32_t s_chunk, s_prefix, s_total;
   __shared__ uint32_t s_cnt[kWaves];
+  __shared__ int32_t s_pvx[kPV], s_pvy[kPV];
+  __shared__ float s_qx[kWaves][kQ], s_qy[kWaves][kQ];
+  __shared__ uint32_t s_qg[kWaves][kQ];
   const Octagon* __restrict__ o = &hdr->oct;
   uint32_t* __restrict__ vidx = hdr->vidx;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
   if (threadIdx.x == 0) s_chunk = atomicAdd(&hdr->tile_ctr, 1u);
+  // The sample polygon (hull path only): a point strictly inside it is
+  // dropped even when it lies outside the octagon.
+  const uint32_t pnv = kHull && poly ? min(poly->nv, (uint32_t)kPolyMax) : 0u;
+  const bool use_sp = pnv >= 3;
+  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+  if (use_sp) {
+    for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
+    pcx = (float)poly->cx * (1.0f / kGridF);
+    pcy = (float)poly->cy * (1.0f / kGridF);
+    pr2 = poly->r2;
+  }
   __syncthreads();
   const uint32_t c = s_chunk;
   if (o->status != 0) {
@@ -493,6 +531,40 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   auto put = [&](uint32_t pos, const P& v) {
     if (pos < (uint32_t)kCapW) s_buf[w][pos] = v;
     else staging[sbase + pos] = v;
+  };
+
+  // Hull path: exact tests of queued points, one per lane (cnt <= 64).
+  uint32_t qn = 0;  // queued points of this wave (wave-uniform)
+  auto drain = [&](uint32_t base, uint32_t cnt) {
+    float x = 0.f, y = 0.f;
+    uint32_t gg = 0;
+    if (lane < (int)cnt) { x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; gg = s_qg[w][base + lane]; }
+    wave_sync();  // read before the next pushes reuse the slots
+    bool keep = false;
+    if (lane < (int)cnt) {
+      keep = classify<false>(x, y, gg, o, vidx).keep;
+      if (keep && use_sp)
+        keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+    }
+    const uint64_t b = __ballot(keep);
+    if (b) {
+      if (keep) put(cw + popc64(b & lt), make_payload<P>(gg, x, y));
+      cw += popc64(b);
+    }
+  };
+  auto push = [&](bool q, float x, float y, uint32_t gg) {
+    const uint64_t m = __ballot(q);
+    if (!m) return;
+    if (q) {
+      const uint32_t pos = qn + popc64(m & lt);
+      s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = gg;
+    }
+    qn += popc64(m);
+    wave_sync();
+    if (qn >= 64) {
+      qn -= 64;
+      drain(qn, 64);
+    }
   };
 
   if (k == 0 && head && lane == 0) {
@@ -540,21 +612,33 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
         const bool in0 = (x0 > bxl) & (x0 < bxh) & (y0 > byl) & (y0 < byh);
         const bool in1 = (x1 > bxl) & (x1 < bxh) & (y1 > byl) & (y1 < byh);
         const bool need0 = val0 & !in0, need1 = val1 & !in1;
-        Verdict v0{false, 0}, v1{false, 0};
-        if (__ballot(need0 | need1)) {
-          if (need0) v0 = classify<LABELS>(x0, y0, g, o, vidx);
-          if (need1) v1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
-        }
-        if (LABELS) {
-          if (val0) labels[g] = v0.label;
-          if (val1) labels[g + 1] = v1.label;
-        }
-        const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
-        if (b0 | b1) {
-          const uint32_t rank = cw + popc64(b0 & lt) + popc64(b1 & lt);
-          if (v0.keep) put(rank, make_payload<P>(g, x0, y0));
-          if (v1.keep) put(rank + (v0.keep ? 1u : 0u), make_payload<P>(g + 1, x1, y1));
-          cw += popc64(b0) + popc64(b1);
+        if constexpr (kHull) {
+          if (__ballot(need0 | need1)) {
+            bool t0 = need0, t1 = need1;
+            if (use_sp) {
+              t0 = t0 && !in_disc(x0, y0, pcx, pcy, pr2);
+              t1 = t1 && !in_disc(x1, y1, pcx, pcy, pr2);
+            }
+            push(t0, x0, y0, g);
+            push(t1, x1, y1, g + 1);
+          }
+        } else {
+          Verdict v0{false, 0}, v1{false, 0};
+          if (__ballot(need0 | need1)) {
+            if (need0) v0 = classify<LABELS>(x0, y0, g, o, vidx);
+            if (need1) v1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
+          }
+          if (LABELS) {
+            if (val0) labels[g] = v0.label;
+            if (val1) labels[g + 1] = v1.label;
+          }
+          const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
+          if (b0 | b1) {
+            const uint32_t rank = cw + popc64(b0 & lt) + popc64(b1 & lt);
+            if (v0.keep) put(rank, make_payload<P>(g, x0, y0));
+            if (v1.keep) put(rank + (v0.keep ? 1u : 0u), make_payload<P>(g + 1, x1, y1));
+            cw += popc64(b0) + popc64(b1);
+          }
         }
       }
     }
@@ -562,6 +646,9 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
 #pragma unroll
     for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
     r = rn;
+  }
+  if constexpr (kHull) {
+    if (qn) drain(0, qn);
   }
   if (lane == 0) s_cnt[w] = cw;
   __syncthreads();
@@ -654,7 +741,7 @@ __global__ void k_set_u32(uint32_t* __restrict__ p, uint32_t v) {
 //
 // Thousands of independent sets in one stream-ordered sequence of kernels
 // (capturable in a graph, no host synchronisation): a plan kernel cuts every
-// set into tiles of kBatchTile points; pass 1 reduces tiles (workgroups take
+// set into tiles of `tile` points; pass 1 reduces tiles (workgroups take
 // tiles with a fixed stride, no shared counter) and folds them into the set's
 // keys with 64-bit atomic max on an order-preserving encoding; one wave per
 // set builds its octagon; pass 2 filters tiles and appends survivor records
@@ -674,6 +761,7 @@ __device__ __forceinline__ double dec_f64(uint64_t e) {
 // group of sets; one exclusive scan gives every group its first tile.
 __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restrict__ off,
                                                        uint32_t nsets, uint64_t total_points,
+                                                       uint32_t tile,
                                                        BatchHdr* __restrict__ bh,
                                                        SetState* __restrict__ sets,
                                                        SetTile* __restrict__ tiles) {
@@ -690,15 +778,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restric
   uint32_t mine = 0;
   for (uint32_t s = s0; s < s1 && !bad; ++s) {
     const uint64_t n = off[s + 1] - off[s];
-    mine += (uint32_t)((n + kBatchTile - 1) / kBatchTile);
+    mine += (uint32_t)((n + tile - 1) / tile);
   }
   uint32_t total;
   uint32_t t = block_excl_scan(mine, total);
   for (uint32_t s = s0; s < s1; ++s) {
     const uint32_t a = (uint32_t)off[s], b = bad ? a : (uint32_t)off[s + 1];
-    for (uint32_t p = a; p < b; p += kBatchTile) {
+    for (uint32_t p = a; p < b; p += tile) {
       SetTile st;
-      st.set = s; st.begin = p; st.end = p + kBatchTile < b ? p + kBatchTile : b; st.pad = 0;
+      st.set = s; st.begin = p; st.end = b - p > tile ? p + tile : b; st.pad = 0;
       tiles[t++] = st;
     }
     SetState& ss = sets[s];
@@ -797,7 +885,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
                                                          const BatchHdr* __restrict__ bh,
                                                          const SetTile* __restrict__ tiles,
                                                          SetState* __restrict__ sets,
+                                                         const SamplePoly* __restrict__ polys,
                                                          Rec* __restrict__ recs) {
+  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
+  __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
+  __shared__ uint32_t s_qg[kWaves][kQueue];
   const uint32_t ntiles = bh->ntiles;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -807,12 +899,61 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
     const Octagon* __restrict__ o = &ss.oct;
     if (o->status != 0) continue;  // block-uniform
     const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
+    // The set's sample polygon, if it has one (block-uniform).
+    const SamplePoly* __restrict__ sp = &polys[st.set];
+    const uint32_t pnv = min(sp->nv, (uint32_t)kPolyMax);
+    const bool use_sp = pnv >= 3;
+    float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+    __syncthreads();  // the previous tile is done with s_pvx / s_pvy
+    if (use_sp) {
+      for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = sp->vx[i]; s_pvy[i] = sp->vy[i]; }
+      pcx = (float)sp->cx * (1.0f / kGridF);
+      pcy = (float)sp->cy * (1.0f / kGridF);
+      pr2 = sp->r2;
+    }
+    __syncthreads();
     const uint32_t base = (uint32_t)off[st.set];
     const uint32_t a = st.begin, b = st.end;
     const uint32_t a2 = a + (a & 1u);
     const uint32_t npairs = b > a2 ? (b - a2) >> 1 : 0;
     const uint32_t nrows = (npairs + 63) / 64;
     const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * (size_t)a2);
+    // Exact tests through the wave's queue (see kQueue); survivors are
+    // appended to the set's slice with one atomic per 64 tests.
+    uint32_t qn = 0;
+    auto drain = [&](uint32_t qb, uint32_t cnt) {
+      float x = 0.f, y = 0.f;
+      uint32_t gl = 0;
+      if (lane < (int)cnt) { x = s_qx[w][qb + lane]; y = s_qy[w][qb + lane]; gl = s_qg[w][qb + lane]; }
+      wave_sync();
+      bool keep = false;
+      if (lane < (int)cnt) {
+        keep = classify<false>(x, y, gl, o, ss.vidx).keep;
+        if (keep && use_sp)
+          keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+      }
+      const uint64_t bk = __ballot(keep);
+      if (bk) {
+        uint32_t pos = 0;
+        if (lane == 0) pos = atomicAdd(&ss.cnt[0], popc64(bk));
+        pos = __shfl(pos, 0) + popc64(bk & lt);
+        if (keep) recs[base + pos] = make_payload<Rec>(gl, x, y);
+      }
+    };
+    auto push = [&](bool qq, float x, float y, uint32_t gl) {
+      const uint64_t m = __ballot(qq);
+      if (!m) return;
+      if (qq) {
+        const uint32_t pos = qn + popc64(m & lt);
+        s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = gl;
+      }
+      qn += popc64(m);
+      wave_sync();
+      if (qn >= 64) {
+        qn -= 64;
+        drain(qn, 64);
+      }
+    };
     for (uint32_t r = w; r < nrows; r += kWaves) {
       const uint32_t q = r * 64 + lane;
       const bool val = q < npairs;
@@ -821,20 +962,17 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
       const bool in0 = (v.x > bxl) & (v.x < bxh) & (v.y > byl) & (v.y < byh);
       const bool in1 = (v.z > bxl) & (v.z < bxh) & (v.w > byl) & (v.w < byh);
       const bool need0 = val & !in0, need1 = val & !in1;
-      Verdict v0{false, 0}, v1{false, 0};
       if (__ballot(need0 | need1)) {
-        if (need0) v0 = classify<false>(v.x, v.y, g - base, o, ss.vidx);
-        if (need1) v1 = classify<false>(v.z, v.w, g + 1 - base, o, ss.vidx);
-      }
-      const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
-      if (b0 | b1) {
-        uint32_t pos = 0;
-        if (lane == 0) pos = atomicAdd(&ss.cnt[0], popc64(b0) + popc64(b1));
-        pos = __shfl(pos, 0) + popc64(b0 & lt) + popc64(b1 & lt);
-        if (v0.keep) recs[base + pos] = make_payload<Rec>(g - base, v.x, v.y);
-        if (v1.keep) recs[base + pos + (v0.keep ? 1u : 0u)] = make_payload<Rec>(g + 1 - base, v.z, v.w);
+        bool t0 = need0, t1 = need1;
+        if (use_sp) {
+          t0 = t0 && !in_disc(v.x, v.y, pcx, pcy, pr2);
+          t1 = t1 && !in_disc(v.z, v.w, pcx, pcy, pr2);
+        }
+        push(t0, v.x, v.y, g - base);
+        push(t1, v.z, v.w, g + 1 - base);
       }
     }
+    if (qn) drain(0, qn);
     if (threadIdx.x == 0) {
       const uint32_t last = a2 + 2 * npairs;
       uint32_t singles[2];
@@ -844,7 +982,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
       for (int i = 0; i < ns; ++i) {
         const uint32_t g = singles[i];
         const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
-        if (classify<false>(x, y, g - base, o, ss.vidx).keep) {
+        if (classify<false>(x, y, g - base, o, ss.vidx).keep &&
+            !(use_sp && poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF)))) {
           const uint32_t pos = atomicAdd(&ss.cnt[0], 1u);
           recs[base + pos] = make_payload<Rec>(g - base, x, y);
         }
@@ -883,16 +1022,21 @@ uint32_t filter_blocks(uint32_t n, uint32_t max_blocks) {
 }
 
 hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
-                          uint32_t* part_bad, uint32_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad);
+                          uint32_t* part_bad, void* sample_scratch, uint32_t blocks,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad,
+                     static_cast<SampleDirs*>(sample_scratch));
   return hipGetLastError();
 }
 
+// sample_scratch / poly non-null: also build the sample polygon (n >= kSampleN).
 hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
+                            const float* xy, uint32_t n, void* sample_scratch, SamplePoly* poly,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_oct_build, dim3(1), dim3(kBlock), 0, st, partials, part_bad, nparts, hdr, res,
-                     tstat, ntstat);
+  const uint32_t grid = 1 + (sample_scratch ? kSampleBlocks : 0);
+  hipLaunchKernelGGL(k_oct_build, dim3(grid), dim3(kBlock), 0, st, partials, part_bad, nparts, hdr, res,
+                     tstat, ntstat, xy, n, static_cast<SampleDirs*>(sample_scratch), poly);
   return hipGetLastError();
 }
 
@@ -901,18 +1045,20 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
                          uint32_t* staging, hipStream_t st) {
   if (labels)
     hipLaunchKernelGGL((k_filter<true, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
-                       hdr, tstat, blocks, surv, count_out, labels, staging);
+                       hdr, tstat, blocks, surv, count_out, labels, staging,
+                       (const SamplePoly*)nullptr);
   else
     hipLaunchKernelGGL((k_filter<false, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
-                       hdr, tstat, blocks, surv, count_out, labels, staging);
+                       hdr, tstat, blocks, surv, count_out, labels, staging,
+                       (const SamplePoly*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             Rec* staging, hipStream_t st) {
+                             Rec* staging, const SamplePoly* poly, hipStream_t st) {
   hipLaunchKernelGGL((k_filter<false, Rec>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr,
-                     tstat, blocks, surv, count_out, nullptr, staging);
+                     tstat, blocks, surv, count_out, (uint8_t*)nullptr, staging, poly);
   return hipGetLastError();
 }
 
@@ -925,16 +1071,24 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 
 namespace chk {
 
+hipError_t launch_batch_sample(const float* xy, const uint64_t* off, uint32_t nsets,
+                               const BatchHdr* bh, SamplePoly* polys, uint32_t sample_min,
+                               uint32_t grid, hipStream_t st);
+
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
-                                    uint64_t total_points, BatchHdr* bh, SetState* sets,
-                                    SetTile* tiles, Rec* recs, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, bh,
+                                    uint64_t total_points, uint32_t tile, BatchHdr* bh,
+                                    SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
+                                    uint32_t grid, uint32_t sample_min, uint32_t sample_grid,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
                      sets, tiles);
+  hipError_t e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(kBlock), 0, st, xy, bh, tiles, sets);
   hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
                      nsets, bh, sets);
   hipLaunchKernelGGL(k_batch_filter, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets,
-                     recs);
+                     polys, recs);
   return hipGetLastError();
 }
 

@@ -295,19 +295,16 @@ __constant__ int8_t kDirY[16] = {0, 2, 1, 5, 1, 5, 1, 2, 0, -2, -1, -5, -1, -5, 
 // 16 directions. Every vertex of that polygon is a candidate, so a candidate
 // inside it (or on a side without being a vertex) is not a strict hull vertex
 // of the candidates and can be dropped.
+//
+// tile_hull_core expects the `cnt` candidates in sm.px/py/pi (visible to the
+// whole workgroup); tile_hull loads them from records first.
 template <int T>
-__device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, uint32_t base,
-                              uint32_t cnt, uint32_t& nl, uint32_t& nu, Result* tm = nullptr) {
+__device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, uint32_t& nu,
+                                   Result* tm = nullptr) {
   constexpr uint32_t E = T / kBlock;  // items per thread: i = threadIdx.x + e * kBlock
   __shared__ uint64_t s_ext[kWaves][16];
   __shared__ int32_t s_vx[16], s_vy[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // Load the records (raw input kept in px/py/pi until compaction).
-  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
-    const Rec r = in_rec[base + i];
-    sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
-  }
-  __syncthreads();
   if (tm) CH_MARK(tm, 2);
   // Extreme position per direction: max of (dot, -position) per thread, then
   // per wave (DPP), then over the waves.
@@ -449,6 +446,17 @@ __device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, u
   if (tm) CH_MARK(tm, 6);
   if (tm) CH_MARK(tm, 7);
   return nl + (nu > 2 ? nu - 2 : 0);
+}
+
+template <int T>
+__device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, uint32_t base,
+                              uint32_t cnt, uint32_t& nl, uint32_t& nu, Result* tm = nullptr) {
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    const Rec r = in_rec[base + i];
+    sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
+  }
+  __syncthreads();
+  return tile_hull_core<T>(sm, cnt, nl, nu, tm);
 }
 
 // Element k of the counter-clockwise hull: the lower chain, then the upper

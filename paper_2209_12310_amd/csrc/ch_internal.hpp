@@ -75,6 +75,28 @@ struct Rec {           // a candidate hull point: grid coordinates + index
   uint32_t i, pad;
 };
 
+// Refined filter of the hull path: a second inner polygon whose vertices are
+// input points -- the extreme points of a strided sample of the input in
+// kPolyMax (or kBatchDirs) directions -- so a point strictly inside it is not
+// a hull vertex. Tested after the octagon's box through a disc around an
+// inner grid point, then exactly.
+constexpr int kPolyMax = 512;              // directions (and at most vertices), single set
+constexpr uint32_t kSampleN = 65536;       // single set: sample points
+constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
+constexpr uint32_t kSampleBlocks = kSampleN / kSamplePer;
+constexpr uint32_t kSampleMin = 1u << 17;  // ch_hull samples from this many points on
+constexpr uint32_t kBatchDirs = 512;       // batch: directions per set
+constexpr uint32_t kBatchSample = 2048;    // batch: sample points per set
+constexpr uint32_t kBatchSampleMin = 1u << 15;
+
+struct SamplePoly {
+  uint32_t nv;         // vertex count; below 3 the polygon is not used
+  int32_t cx, cy;      // grid point strictly inside the polygon
+  float r2;            // squared radius (float units) of a disc about (cx, cy) inside
+                       // the polygon, rounded down with a margin for fp32 tests
+  int32_t vx[kPolyMax], vy[kPolyMax];  // counter-clockwise, strictly convex
+};
+
 constexpr size_t kHdrBytes = 1024;
 constexpr size_t kResBytes = 1024;
 static_assert(sizeof(Header) <= kHdrBytes, "header too large");
@@ -87,7 +109,7 @@ inline uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) : k
 // Workspace layout. ch_filter uses the prefix up to `filter_end`.
 struct Layout {
   size_t hdr, res, res_idx, partials, part_bad, tstat, staging, filter_end;
-  size_t surv, recA, recB, colbot, coltop, colcnt, lstA, lstB, wcnt, total;
+  size_t surv, recA, recB, colbot, coltop, colcnt, lstA, lstB, wcnt, poly, samp, total;
 };
 
 inline Layout layout(uint32_t n) {
@@ -108,7 +130,7 @@ inline Layout layout(uint32_t n) {
   L.recA = o;      o = align_up(o + m * sizeof(Rec), 256);
   L.recB = o;      o = align_up(o + m * sizeof(Rec), 256);
   if (n <= (uint32_t)kFinalTile) {  // one workgroup: no rounds, no large-hull path
-    L.colbot = L.coltop = L.colcnt = L.lstA = L.lstB = L.wcnt = o;
+    L.colbot = L.coltop = L.colcnt = L.lstA = L.lstB = L.wcnt = L.poly = L.samp = o;
     L.total = o;
     return L;
   }
@@ -120,12 +142,17 @@ inline Layout layout(uint32_t n) {
   L.lstA = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
   L.lstB = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
   L.wcnt = o;      o = align_up(o + 2 * (chain_cap / kHullTile + 4) * 4, 256);
+  // Refined filter: the sample polygon and the direction maxima.
+  L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
+  L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256, 256);
   L.total = o;
   return L;
 }
 
 // ---------------------------------------------------------------- batch mode
-constexpr uint32_t kBatchTile = 8192;     // points per pass-1/pass-2 tile of one set
+constexpr uint32_t kBatchTile = 8192;     // default points per pass-1/pass-2 tile of one set
+constexpr uint32_t kBatchTileMin = 4096;  // smallest tile the workspace is sized for
+constexpr uint32_t kBatchTileMax = 65536;
 constexpr int kBatchRounds = 4;           // tile-hull rounds for sets with many survivors
 constexpr uint32_t kCountOverflow = 0xFFFFFFFEu;
 constexpr uint32_t kCountInvalid = 0xFFFFFFFDu;
@@ -153,16 +180,17 @@ struct SetState {
 };
 
 struct BatchLayout {
-  size_t hdr, sets, tiles, rtiles, recA, recB, total;
+  size_t hdr, sets, polys, tiles, rtiles, recA, recB, total;
 };
 
 inline BatchLayout batch_layout(uint32_t nsets, uint64_t total_points) {
   BatchLayout L{};
   size_t o = 0;
-  const size_t ntiles = total_points / kBatchTile + nsets + 1;
+  const size_t ntiles = total_points / kBatchTileMin + nsets + 1;
   const size_t nrt = total_points / 2048 + nsets + 1;
   L.hdr = o;    o = align_up(o + sizeof(BatchHdr), 256);
   L.sets = o;   o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SetState), 256);
+  L.polys = o;  o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SamplePoly), 256);
   L.tiles = o;  o = align_up(o + ntiles * sizeof(SetTile), 256);
   L.rtiles = o; o = align_up(o + nrt * sizeof(SetTile), 256);
   const size_t m = total_points ? total_points : 1;

@@ -118,3 +118,77 @@ def test_batch_config_scaled(ctx):
     xy, off, kinds = workloads.batch_sets(4096, 3, scale=0.05)
     sets = [xy[int(off[s]): int(off[s + 1])] for s in range(4096)]
     _check_sets(ctx, sets)
+
+
+def _mixed_batch(seed, count, hi=80000):
+    rng = np.random.default_rng(seed)
+    sets = [workloads.by_kind(("uniform", "normal", "annulus_wide")[i % 3], int(n), seed + i)
+            for i, n in enumerate(rng.integers(0, hi, count))]
+    off = np.zeros(count + 1, np.int64)
+    off[1:] = np.cumsum([s.shape[0] for s in sets])
+    return sets, off
+
+
+@pytest.mark.parametrize("params", [
+    {"tile_points": 4096, "pass_blocks": 1, "hull_blocks": 1, "sample_min": 0},
+    {"tile_points": 65536, "pass_blocks": 7, "hull_blocks": 5, "sample_min": 0xFFFFFFFF},
+    {"tile_points": 16384, "pass_blocks": 2048, "hull_blocks": 2048, "sample_min": 40000},
+])
+def test_launch_parameters_do_not_change_results(ctx, params):
+    _say(f"batch params {params}")
+    import torch
+    sets, off = _mixed_batch(300, 25)
+    ctx.set_batch_params(params)
+    try:
+        assert ctx.batch_params(25, int(off[-1])) == params
+        t = torch.from_numpy(np.concatenate(sets)).to("cuda:0")
+        idx, cnt = ctx.hull_batch(t, torch.from_numpy(off).to("cuda:0"))
+        for s, pts in enumerate(sets):
+            assert np.array_equal(idx[off[s]: off[s] + cnt[s]], oracle.hull(pts)), s
+    finally:
+        ctx.set_batch_params(None)
+
+
+def test_invalid_launch_parameters(ctx):
+    import paper_2209_12310_amd as ch
+    for bad in ({"tile_points": 5000, "pass_blocks": 1, "hull_blocks": 1, "sample_min": 0},
+                {"tile_points": 2048, "pass_blocks": 1, "hull_blocks": 1, "sample_min": 0},
+                {"tile_points": 8192, "pass_blocks": 0, "hull_blocks": 1, "sample_min": 0}):
+        with pytest.raises(ch.ConvexHullError):
+            ctx.set_batch_params(bad)
+
+
+def test_tuner_and_cache(tmp_path):
+    """The tuner returns valid parameters, leaves the batch's result in the
+    outputs, and its cache file gives a new context the same choice."""
+    _say("batch tuner")
+    import torch
+    import paper_2209_12310_amd as ch
+    cache = str(tmp_path / "tune.txt")
+    sets, off = _mixed_batch(400, 60, 150000)
+    n, nsets = int(off[-1]), len(sets)
+    t = torch.from_numpy(np.concatenate(sets)).to("cuda:0")
+    o = torch.from_numpy(off).to("cuda:0")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    cnt = torch.empty(nsets, dtype=torch.int32, device="cuda:0")
+    c1 = ch.Context(0, tune_cache=cache)
+    try:
+        best = c1.tune_batch(t, o, idx, cnt)
+        torch.cuda.synchronize()
+        counts = cnt.cpu().numpy().view(np.uint32)
+        hidx = idx.cpu().numpy().view(np.uint32)
+        for s, pts in enumerate(sets):
+            assert np.array_equal(hidx[off[s]: off[s] + counts[s]], oracle.hull(pts)), s
+        assert c1.batch_params(nsets, n) == best
+        lines = open(cache).read().split("\n")
+        assert any(line.startswith("convhull-tune 1 ") for line in lines)
+    finally:
+        c1.close()
+    c2 = ch.Context(0, tune_cache=cache)
+    try:
+        assert c2.batch_params(nsets, n) == best
+        got_idx, got_cnt = c2.hull_batch(t, o)
+        for s, pts in enumerate(sets):
+            assert np.array_equal(got_idx[off[s]: off[s] + got_cnt[s]], oracle.hull(pts)), s
+    finally:
+        c2.close()
