@@ -28,8 +28,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "Mpts/s end-to-end hull at 1e8 pts (% HBM peak); batched hulls/s + p50/p99"
 WORKLOAD = "normal_1e8"
 # Algorithmic bytes per point: pass 1 reads 8 B, pass 2 reads 8 B; each
-# survivor adds a 4 B index write (and the hull pass reads it back with its
-# point).
+# candidate pass 2 keeps adds a 16 B record write (grid coordinates and
+# index), which the hull pass reads back. The octagon's survivor count bounds
+# the candidates from above (the hull path's refined filter only removes).
 BYTES_PER_POINT = {"reduce8": 8, "filter_compact": 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_normal_1e8.json")
 KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp"]
@@ -360,7 +361,7 @@ def main() -> int:
     dom = max((k for k in BYTES_PER_POINT if k in stats), key=lambda k: stats[k][1])
     launches, total_ms = stats[dom]
     mean_s = total_ms / launches * 1e-3
-    alg_bytes = BYTES_PER_POINT[dom] * n + (4 * survivors if dom == "filter_compact" else 0)
+    alg_bytes = BYTES_PER_POINT[dom] * n + (16 * survivors if dom == "filter_compact" else 0)
     achieved = alg_bytes / mean_s / 1e9
     traffic = load_traffic(n, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

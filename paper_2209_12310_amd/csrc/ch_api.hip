@@ -33,8 +33,8 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
                          uint32_t* staging, hipStream_t st);
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
-                             uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             Rec* staging, const SamplePoly* poly, hipStream_t st);
+                             uint32_t blocks, Rec* surv, uint32_t* count_out,
+                             const SamplePoly* poly, hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -196,7 +196,7 @@ T* at(void* ws, size_t off) {
 // kSampleMin the octagon build also builds the refined filter's polygon.
 ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
                      uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
-                     hipStream_t st, Rec* surv_rec = nullptr, Rec* rec_staging = nullptr) {
+                     hipStream_t st, Rec* surv_rec = nullptr) {
   const bool sample = surv_rec && n >= kSampleMin;
   SamplePoly* poly = sample ? at<SamplePoly>(ws, L.poly) : nullptr;
   void* scratch = sample ? at<void>(ws, L.samp) : nullptr;
@@ -221,8 +221,7 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
   {
     ProfScope p(ctx, st, "filter_compact");
     if (surv_rec)
-      e = launch_filter_rec(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv_rec, count_out,
-                            rec_staging, poly, st);
+      e = launch_filter_rec(d_xy, n, head, hdr, g1, surv_rec, count_out, poly, st);
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);
@@ -499,9 +498,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
   Rec* srec = at<Rec>(d_ws, L.surv);
   Rec* rec[2] = {at<Rec>(d_ws, L.recA), at<Rec>(d_ws, L.recB)};
-  // The survivor records' overflow staging reuses list B (first written by round 1).
-  if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec,
-                               rec[1]))
+  if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec))
     return s;
 
   const Result* hres = reinterpret_cast<const Result*>(ctx->pinned);

@@ -427,7 +427,8 @@ __device__ __forceinline__ Verdict classify(float x, float y, uint32_t gidx,
 
 __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
-// Pass 2: persistent grid of G2 workgroups. Workgroup ids come from
+// Pass 2 of ch_filter (the survivor list in ascending index order; the hull
+// path uses k_filter_hull below): persistent grid of G2 workgroups. Workgroup ids come from
 // hdr->tile_ctr in start order; workgroup c owns waves 4c..4c+3 and wave k
 // streams the contiguous rows [k*RW, (k+1)*RW) of 64 pairs, so the survivors
 // of the waves, concatenated in wave order, are in ascending index order.
@@ -436,7 +437,8 @@ __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popc
 // the counts of all earlier workgroups (look-back over at most G2 words, all
 // loaded at once), and copies its survivors to their final place.
 // Survivor payloads: the index alone (ch_filter), or a record with the grid
-// coordinates (the hull pass then never gathers from the point array).
+// coordinates (hull path and batch mode: the hull pass then never gathers
+// from the point array).
 template <class P>
 __device__ __forceinline__ P make_payload(uint32_t g, float x, float y);
 template <>
@@ -457,8 +459,8 @@ template <class P>
 struct StageCap {
   static constexpr int value = 8192 / (int)sizeof(P);  // 8 KiB of LDS per wave
 };
-// Records leave room for the sample polygon and the exact-test queue within
-// 40 KiB per workgroup (four workgroups per CU).
+// Records (k_filter_hull) leave room for the sample polygon and the
+// exact-test queue within 40 KiB per workgroup (four workgroups per CU).
 template <>
 struct StageCap<Rec> {
   static constexpr int value = 448;
@@ -476,34 +478,16 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
                                                    P* __restrict__ surv,
                                                    uint32_t* __restrict__ count_out,
                                                    uint8_t* __restrict__ labels,
-                                                   P* __restrict__ staging,
-                                                   const SamplePoly* __restrict__ poly) {
+                                                   P* __restrict__ staging) {
   constexpr int kCapW = StageCap<P>::value;
-  constexpr bool kHull = sizeof(P) == sizeof(Rec);  // hull path: records, queue, sample polygon
-  constexpr int kQ = kHull ? kQueue : 1;
-  constexpr int kPV = kHull ? kPolyMax : 1;
   __shared__ P s_buf[kWaves][kCapW];
   __shared__ uint32_t s_chunk, s_prefix, s_total;
   __shared__ uint32_t s_cnt[kWaves];
-  __shared__ int32_t s_pvx[kPV], s_pvy[kPV];
-  __shared__ float s_qx[kWaves][kQ], s_qy[kWaves][kQ];
-  __shared__ uint32_t s_qg[kWaves][kQ];
   const Octagon* __restrict__ o = &hdr->oct;
   uint32_t* __restrict__ vidx = hdr->vidx;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
   if (threadIdx.x == 0) s_chunk = atomicAdd(&hdr->tile_ctr, 1u);
-  // The sample polygon (hull path only): a point strictly inside it is
-  // dropped even when it lies outside the octagon.
-  const uint32_t pnv = kHull && poly ? min(poly->nv, (uint32_t)kPolyMax) : 0u;
-  const bool use_sp = pnv >= 3;
-  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
-  if (use_sp) {
-    for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
-    pcx = (float)poly->cx * (1.0f / kGridF);
-    pcy = (float)poly->cy * (1.0f / kGridF);
-    pr2 = poly->r2;
-  }
   __syncthreads();
   const uint32_t c = s_chunk;
   if (o->status != 0) {
@@ -531,40 +515,6 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   auto put = [&](uint32_t pos, const P& v) {
     if (pos < (uint32_t)kCapW) s_buf[w][pos] = v;
     else staging[sbase + pos] = v;
-  };
-
-  // Hull path: exact tests of queued points, one per lane (cnt <= 64).
-  uint32_t qn = 0;  // queued points of this wave (wave-uniform)
-  auto drain = [&](uint32_t base, uint32_t cnt) {
-    float x = 0.f, y = 0.f;
-    uint32_t gg = 0;
-    if (lane < (int)cnt) { x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; gg = s_qg[w][base + lane]; }
-    wave_sync();  // read before the next pushes reuse the slots
-    bool keep = false;
-    if (lane < (int)cnt) {
-      keep = classify<false>(x, y, gg, o, vidx).keep;
-      if (keep && use_sp)
-        keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
-    }
-    const uint64_t b = __ballot(keep);
-    if (b) {
-      if (keep) put(cw + popc64(b & lt), make_payload<P>(gg, x, y));
-      cw += popc64(b);
-    }
-  };
-  auto push = [&](bool q, float x, float y, uint32_t gg) {
-    const uint64_t m = __ballot(q);
-    if (!m) return;
-    if (q) {
-      const uint32_t pos = qn + popc64(m & lt);
-      s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = gg;
-    }
-    qn += popc64(m);
-    wave_sync();
-    if (qn >= 64) {
-      qn -= 64;
-      drain(qn, 64);
-    }
   };
 
   if (k == 0 && head && lane == 0) {
@@ -612,33 +562,21 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
         const bool in0 = (x0 > bxl) & (x0 < bxh) & (y0 > byl) & (y0 < byh);
         const bool in1 = (x1 > bxl) & (x1 < bxh) & (y1 > byl) & (y1 < byh);
         const bool need0 = val0 & !in0, need1 = val1 & !in1;
-        if constexpr (kHull) {
-          if (__ballot(need0 | need1)) {
-            bool t0 = need0, t1 = need1;
-            if (use_sp) {
-              t0 = t0 && !in_disc(x0, y0, pcx, pcy, pr2);
-              t1 = t1 && !in_disc(x1, y1, pcx, pcy, pr2);
-            }
-            push(t0, x0, y0, g);
-            push(t1, x1, y1, g + 1);
-          }
-        } else {
-          Verdict v0{false, 0}, v1{false, 0};
-          if (__ballot(need0 | need1)) {
-            if (need0) v0 = classify<LABELS>(x0, y0, g, o, vidx);
-            if (need1) v1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
-          }
-          if (LABELS) {
-            if (val0) labels[g] = v0.label;
-            if (val1) labels[g + 1] = v1.label;
-          }
-          const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
-          if (b0 | b1) {
-            const uint32_t rank = cw + popc64(b0 & lt) + popc64(b1 & lt);
-            if (v0.keep) put(rank, make_payload<P>(g, x0, y0));
-            if (v1.keep) put(rank + (v0.keep ? 1u : 0u), make_payload<P>(g + 1, x1, y1));
-            cw += popc64(b0) + popc64(b1);
-          }
+        Verdict v0{false, 0}, v1{false, 0};
+        if (__ballot(need0 | need1)) {
+          if (need0) v0 = classify<LABELS>(x0, y0, g, o, vidx);
+          if (need1) v1 = classify<LABELS>(x1, y1, g + 1, o, vidx);
+        }
+        if (LABELS) {
+          if (val0) labels[g] = v0.label;
+          if (val1) labels[g + 1] = v1.label;
+        }
+        const uint64_t b0 = __ballot(v0.keep), b1 = __ballot(v1.keep);
+        if (b0 | b1) {
+          const uint32_t rank = cw + popc64(b0 & lt) + popc64(b1 & lt);
+          if (v0.keep) put(rank, make_payload<P>(g, x0, y0));
+          if (v1.keep) put(rank + (v0.keep ? 1u : 0u), make_payload<P>(g + 1, x1, y1));
+          cw += popc64(b0) + popc64(b1);
         }
       }
     }
@@ -646,9 +584,6 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
 #pragma unroll
     for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
     r = rn;
-  }
-  if constexpr (kHull) {
-    if (qn) drain(0, qn);
   }
   if (lane == 0) s_cnt[w] = cw;
   __syncthreads();
@@ -721,6 +656,150 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   const uint32_t nb = cw < (uint32_t)kCapW ? cw : (uint32_t)kCapW;
   for (uint32_t i = lane; i < nb; i += 64) surv[off + i] = s_buf[w][i];
   for (uint32_t i = kCapW + lane; i < cw; i += 64) surv[off + i] = staging[sbase + i];
+}
+
+// Pass 2 of the hull path. The hull pass sorts its candidates, so their order
+// is free: the grid walks the points exactly as pass 1 does (each wave takes
+// every nw-th batch of kU rows, next batch's loads issued before the current
+// one is tested), tests them (octagon box, sample-polygon disc, then the
+// per-wave queue of exact tests), stages survivor records per wave in LDS and
+// flushes them to `surv` with one atomic reservation per flush -- no ordering
+// and no look-back. The head point and an odd last point go to workgroup 0.
+__global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict__ xy, uint32_t n,
+                                                        uint32_t head, Header* __restrict__ hdr,
+                                                        Rec* __restrict__ surv,
+                                                        uint32_t* __restrict__ count_out,
+                                                        const SamplePoly* __restrict__ poly) {
+  constexpr int kCapW = StageCap<Rec>::value;
+  __shared__ Rec s_buf[kWaves][kCapW];
+  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
+  __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
+  __shared__ uint32_t s_qg[kWaves][kQueue];
+  const Octagon* __restrict__ o = &hdr->oct;
+  uint32_t* __restrict__ vidx = hdr->vidx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  if (o->status != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
+    return;
+  }
+  const uint32_t pnv = poly ? min(poly->nv, (uint32_t)kPolyMax) : 0u;
+  const bool use_sp = pnv >= 3;
+  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+  if (use_sp) {
+    for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
+    pcx = (float)poly->cx * (1.0f / kGridF);
+    pcy = (float)poly->cy * (1.0f / kGridF);
+    pr2 = poly->r2;
+  }
+  __syncthreads();
+  const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
+
+  uint32_t cw = 0, qn = 0;  // staged survivors, queued points (wave-uniform)
+  auto flush = [&]() {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(count_out, cw);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < cw; i += 64) surv[base + i] = s_buf[w][i];
+    wave_sync();
+    cw = 0;
+  };
+  auto exact_keep = [&](float x, float y, uint32_t g) {
+    bool keep = classify<false>(x, y, g, o, vidx).keep;
+    if (keep && use_sp)
+      keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+    return keep;
+  };
+  auto drain = [&](uint32_t base, uint32_t cnt) {
+    float x = 0.f, y = 0.f;
+    uint32_t g = 0;
+    if (lane < (int)cnt) { x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; g = s_qg[w][base + lane]; }
+    wave_sync();
+    const bool keep = lane < (int)cnt && exact_keep(x, y, g);
+    const uint64_t b = __ballot(keep);
+    if (!b) return;
+    if (cw + popc64(b) > (uint32_t)kCapW) flush();
+    if (keep) s_buf[w][cw + popc64(b & lt)] = make_payload<Rec>(g, x, y);
+    cw += popc64(b);
+  };
+  auto push = [&](bool q, float x, float y, uint32_t g) {
+    const uint64_t m = __ballot(q);
+    if (!m) return;
+    if (q) {
+      const uint32_t pos = qn + popc64(m & lt);
+      s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = g;
+    }
+    qn += popc64(m);
+    wave_sync();
+    if (qn >= 64) {
+      qn -= 64;
+      drain(qn, 64);
+    }
+  };
+  auto test_pair = [&](const float4& v, uint32_t q, bool val) {
+    const uint32_t g = head + 2 * q;
+    const bool in0 = (v.x > bxl) & (v.x < bxh) & (v.y > byl) & (v.y < byh);
+    const bool in1 = (v.z > bxl) & (v.z < bxh) & (v.w > byl) & (v.w < byh);
+    bool t0 = val & !in0, t1 = val & !in1;
+    if (__ballot(t0 | t1)) {
+      if (use_sp) {
+        t0 = t0 && !in_disc(v.x, v.y, pcx, pcy, pr2);
+        t1 = t1 && !in_disc(v.z, v.w, pcx, pcy, pr2);
+      }
+      push(t0, v.x, v.y, g);
+      push(t1, v.z, v.w, g + 1);
+    }
+  };
+
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
+  const uint32_t nfull = (n - head) >> 1;
+  const uint32_t gw = blockIdx.x * kWaves + w;
+  const uint32_t nw = gridDim.x * kWaves;
+  const uint32_t per_batch = kU * 64;
+  const uint32_t nbatch = (nfull + per_batch - 1) / per_batch;
+  if (gw < nbatch) {
+    float4 cur[kU], nxt[kU];
+    uint32_t b = gw;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t q = b * per_batch + u * 64 + lane;
+      cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+    }
+    while (true) {
+      const uint32_t bn = b + nw;
+      const bool more = bn < nbatch;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t q = bn * per_batch + u * 64 + lane;
+          nxt[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t q = b * per_batch + u * 64 + lane;
+        test_pair(cur[u], q, q < nfull);
+      }
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+      b = bn;
+    }
+  }
+  if (qn) drain(0, qn);
+  if (cw) flush();
+  // The head point (xy 8 mod 16 bytes aligned) and an odd last point.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    uint32_t single[2];
+    int ns = 0;
+    if (head) single[ns++] = 0;
+    if ((n - head) & 1) single[ns++] = n - 1;
+    for (int i = 0; i < ns; ++i) {
+      const uint32_t g = single[i];
+      const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
+      if (exact_keep(x, y, g)) surv[atomicAdd(count_out, 1u)] = make_payload<Rec>(g, x, y);
+    }
+  }
 }
 
 // Copies the octagon (coordinates and smallest indices) to a caller buffer.
@@ -1045,20 +1124,18 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
                          uint32_t* staging, hipStream_t st) {
   if (labels)
     hipLaunchKernelGGL((k_filter<true, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
-                       hdr, tstat, blocks, surv, count_out, labels, staging,
-                       (const SamplePoly*)nullptr);
+                       hdr, tstat, blocks, surv, count_out, labels, staging);
   else
     hipLaunchKernelGGL((k_filter<false, uint32_t>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head,
-                       hdr, tstat, blocks, surv, count_out, labels, staging,
-                       (const SamplePoly*)nullptr);
+                       hdr, tstat, blocks, surv, count_out, labels, staging);
   return hipGetLastError();
 }
 
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
-                             uint64_t* tstat, uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             Rec* staging, const SamplePoly* poly, hipStream_t st) {
-  hipLaunchKernelGGL((k_filter<false, Rec>), dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr,
-                     tstat, blocks, surv, count_out, (uint8_t*)nullptr, staging, poly);
+                             uint32_t blocks, Rec* surv, uint32_t* count_out,
+                             const SamplePoly* poly, hipStream_t st) {
+  hipLaunchKernelGGL(k_filter_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, surv,
+                     count_out, poly);
   return hipGetLastError();
 }
 
