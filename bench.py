@@ -8,8 +8,9 @@ hull, hull indices back in host memory.
 
 Prints one JSON line (see the design notes for every field). Roofline: the
 dominant kernel's algorithmic bytes per launch divided by its mean duration,
-timed with HIP events recorded by the library on the launch stream during the
-timed region.
+timed with HIP events recorded by the library on the launch stream in a
+second region of the same steps (the end-to-end figure is taken without
+them).
 """
 from __future__ import annotations
 
@@ -27,11 +28,27 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "Mpts/s end-to-end hull at 1e8 pts (% HBM peak); batched hulls/s + p50/p99"
 WORKLOAD = "normal_1e8"
-# Algorithmic bytes per point: pass 1 reads 8 B, pass 2 reads 8 B; each
-# candidate pass 2 keeps adds a 16 B record write (grid coordinates and
-# index), which the hull pass reads back. The octagon's survivor count bounds
-# the candidates from above (the hull path's refined filter only removes).
-BYTES_PER_POINT = {"reduce8": 8, "filter_compact": 8}
+# Streaming kernels of the filtering stage and the point bytes each reads.
+# From 131072 points ch_hull reads the points once (pass_fused: the extreme
+# reduction and the sample-polygon test together) and writes 16 B candidate
+# records; below that, or without a usable sample polygon, pass 1 (reduce8)
+# and pass 2 (filter_compact) each read 8 B per point.
+BYTES_PER_POINT = {"reduce8": 8, "filter_compact": 8, "pass_fused": 8}
+STAGE_KERNELS = ("sample_poly", "pass_fused", "reduce8", "oct_build", "cand_filter", "filter_compact")
+
+
+def stage_bytes(n: int, info: dict) -> dict:
+    """Algorithmic HBM bytes of one ch_hull filtering stage, from the call's
+    counts: point reads, the sample gather (8 B per sample point), candidate
+    records written and read back, survivor records written."""
+    cand, surv = info["candidates"], info["survivors"]
+    if cand:
+        b = {"points": 8 * n, "sample": 8 * 65536, "candidates": 32 * cand, "survivors": 16 * surv}
+    else:
+        b = {"points": 16 * n, "sample": 0, "candidates": 0, "survivors": 16 * surv}
+    b["total"] = sum(b.values())
+    b["per_point"] = round(b["total"] / n, 3)
+    return b
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_normal_1e8.json")
 KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp"]
 
@@ -116,10 +133,13 @@ def bench_single(ctx, name: str, steps: int, warmup: int) -> dict:
         hull = ctx.hull(t)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
+    info = ctx.last_hull_info()
+    moved = stage_bytes(n, info)["total"] + 16 * info["survivors"]
     del t
     return {"workload": name, "n": n, "ms_per_step": round(ms, 4), "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
-            "hbm_frac_16B_per_pt": round(16 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "octagon_survivors": survivors, "h": int(hull.size)}
+            "bytes_per_point": round(moved / n, 3),
+            "hbm_frac": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "octagon_survivors": survivors, "hull_info": info, "h": int(hull.size)}
 
 
 def pct(vals, q):
@@ -356,22 +376,31 @@ def main() -> int:
     ctx.profile_enable(False)
     stats = ctx.profile_read()
 
+    info = ctx.last_hull_info()
     kernels = {k: {"launches": v[0], "mean_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
                for k, v in stats.items() if v[0]}
     dom = max((k for k in BYTES_PER_POINT if k in stats), key=lambda k: stats[k][1])
     launches, total_ms = stats[dom]
     mean_s = total_ms / launches * 1e-3
-    alg_bytes = BYTES_PER_POINT[dom] * n + (16 * survivors if dom == "filter_compact" else 0)
+    if dom == "pass_fused":
+        alg_bytes = 8 * n + 16 * info["candidates"]
+    elif dom == "filter_compact":
+        alg_bytes = 8 * n + 16 * info["survivors"]
+    else:
+        alg_bytes = 8 * n
     achieved = alg_bytes / mean_s / 1e9
     traffic = load_traffic(n, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
                 "mean_us": round(mean_s * 1e6, 2)}
-    filt_ms = sum(stats[k][1] / stats[k][0] for k in BYTES_PER_POINT if k in stats and stats[k][0])
-    filter_stage = {"bytes_per_point": 16, "mean_us": round(filt_ms * 1e3, 2),
-                    "gbs": round(16 * n / (filt_ms * 1e-3) / 1e9, 1),
-                    "frac_of_peak": round(16 * n / (filt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    sb = stage_bytes(n, info)
+    filt_ms = sum(stats[k][1] / stats[k][0] for k in STAGE_KERNELS if k in stats and stats[k][0])
+    filter_stage = {"bytes_per_point": sb["per_point"], "bytes": sb, "mean_us": round(filt_ms * 1e3, 2),
+                    "gbs": round(sb["total"] / (filt_ms * 1e-3) / 1e9, 1),
+                    "frac_of_peak": round(sb["total"] / (filt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "kernels": [k for k in STAGE_KERNELS if k in stats]}
+    moved = sb["total"] + 16 * info["survivors"]  # plus the hull pass reading the survivors
 
     out = {
         "metric": METRIC,
@@ -389,7 +418,9 @@ def main() -> int:
         "config": {"workload": WORKLOAD, "n": n, "distribution": "normal mean 0.5 sigma 0.1, "
                    "float32 on the 2^-20 grid in [0,1)", "seed": 1, "survivors": survivors,
                    "h": int(hull.size)},
-        "hbm_frac_end_to_end": round(16 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bytes_per_point_end_to_end": round(moved / n, 3),
+        "hbm_frac_end_to_end": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hull_info": info,
         "filter_stage": filter_stage,
         "roofline": roofline,
         "kernels": kernels,
@@ -398,8 +429,10 @@ def main() -> int:
     torch.cuda.synchronize()
     out["single_sets"] = {WORKLOAD: {"workload": WORKLOAD, "n": n, "ms_per_step": round(ms, 4),
                                      "mpts_per_s": round(value, 1),
-                                     "hbm_frac_16B_per_pt": out["hbm_frac_end_to_end"],
-                                     "octagon_survivors": survivors, "h": int(hull.size)}}
+                                     "bytes_per_point": out["bytes_per_point_end_to_end"],
+                                     "hbm_frac": out["hbm_frac_end_to_end"],
+                                     "octagon_survivors": survivors, "hull_info": info,
+                                     "h": int(hull.size)}}
     if not args.no_extra:
         for name in ("uniform_1e6", "annulus_1e8"):
             out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 2)

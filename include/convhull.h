@@ -130,6 +130,21 @@ ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_surv
 ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_idx, uint32_t cap,
                   uint32_t* h_out, void* d_ws, size_t ws_bytes, void* stream);
 
+/* What the last successful ch_hull on this context did: n; the candidate
+ * records of the refined filter's single read (0 when it was not used: below
+ * 131072 points, or no usable sample polygon); the records left after the
+ * octagon test (the hull pass's input); the tile-hull rounds; whether the
+ * large-hull path ran; h. Diagnostics only. */
+typedef struct {
+  uint32_t n;
+  uint32_t candidates;
+  uint32_t survivors;
+  uint32_t rounds;
+  uint32_t large_path;
+  uint32_t h;
+} ch_hull_info;
+ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out);
+
 /* Count values ch_hull_batch writes for a set it could not finish:
  * CH_COUNT_DOMAIN_ERROR (above) for a domain error in that set;
  * CH_COUNT_OVERFLOW when the set's candidates did not shrink to one workgroup

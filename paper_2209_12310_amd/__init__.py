@@ -166,6 +166,12 @@ class Context:
             self._raise(st)
         return out[: h.value].copy()
 
+    def last_hull_info(self) -> dict:
+        """Counts of the last successful hull() on this context."""
+        info = _capi.HullInfo()
+        self._lib.ch_last_hull_info(self._h, ctypes.byref(info))
+        return {f: getattr(info, f) for f, _ in _capi.HullInfo._fields_}
+
     def hull_batch_async(self, xy, off, hull_idx, hull_count, ws=None):
         """ch_hull_batch on device tensors: xy (N,2) float32, off (nsets+1)
         int64 (uint64 offsets), hull_idx (N,) int32, hull_count (nsets,) int32.

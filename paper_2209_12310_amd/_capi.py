@@ -47,6 +47,11 @@ class BatchParams(ctypes.Structure):
                 ("hull_blocks", ctypes.c_uint32), ("sample_min", ctypes.c_uint32)]
 
 
+class HullInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("candidates", ctypes.c_uint32), ("survivors", ctypes.c_uint32),
+                ("rounds", ctypes.c_uint32), ("large_path", ctypes.c_uint32), ("h", ctypes.c_uint32)]
+
+
 class ServeConfig(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_uint32), ("n_streams", ctypes.c_int),
@@ -68,6 +73,7 @@ SIGNATURES = {
     "ch_hull_workspace_bytes": (SZ, [U32]),
     "ch_filter": (I32, [P, P, U32, P, P, P, P, P, SZ, P]),
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
+    "ch_last_hull_info": (I32, [P, ctypes.POINTER(HullInfo)]),
     "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),
     "ch_hull_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P]),
     "ch_batch_params_get": (I32, [P, U32, U64, ctypes.POINTER(BatchParams)]),

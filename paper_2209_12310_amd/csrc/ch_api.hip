@@ -22,19 +22,25 @@ hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);
 uint32_t reduce_blocks(uint32_t n, uint32_t max_blocks);
 uint32_t filter_blocks(uint32_t n, uint32_t max_blocks);
 hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
-                          uint32_t* part_bad, void* sample_scratch, uint32_t blocks,
-                          hipStream_t st);
+                          uint32_t* part_bad, uint32_t blocks, hipStream_t st);
 hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
-                            const float* xy, uint32_t n, void* sample_scratch, SamplePoly* poly,
                             hipStream_t st);
+hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
+                              hipStream_t st);
+hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
+                            uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
+                            uint32_t blocks, hipStream_t st);
+hipError_t launch_cand_filter(const Rec* cand, const void* scratch, const SamplePoly* gate,
+                              Header* hdr, Rec* surv, uint32_t* count_out, uint32_t* ncand_out,
+                              uint32_t blocks, hipStream_t st);
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
                          uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
                          uint32_t* staging, hipStream_t st);
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             const SamplePoly* poly, hipStream_t st);
+                             const SamplePoly* gate, hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -82,6 +88,7 @@ struct ch_ctx {
   uint32_t filter_max_blocks = 1024;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   std::string err;
+  ch_hull_info last{};  // counts of the last successful ch_hull
   // Batch-mode parameters: fixed ones (ch_batch_params_set), else the tuned
   // entry nearest to the call's shape, else the defaults.
   ch_batch_params batch{};
@@ -191,33 +198,53 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<unsigned char*>(ws) + off);
 }
 
-// Enqueues pass 1 (reduce + octagon build) and pass 2 (filter + compaction).
-// With surv_rec (the hull path) the survivors are records, and for n >=
-// kSampleMin the octagon build also builds the refined filter's polygon.
+// Enqueues the filtering stage. ch_filter (surv_rec null): pass 1 (extreme
+// reduction, octagon build) and the ordered pass 2. Hull path (records into
+// surv_rec): below kSampleMin points, pass 1 and the unordered pass 2; from
+// kSampleMin on, the sample polygon first, then one fused read (pass 1 plus
+// the polygon test), the octagon build, and the octagon test on the
+// candidates (or, without a usable polygon, the unordered pass 2).
 ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
                      uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
-                     hipStream_t st, Rec* surv_rec = nullptr) {
-  const bool sample = surv_rec && n >= kSampleMin;
-  SamplePoly* poly = sample ? at<SamplePoly>(ws, L.poly) : nullptr;
-  void* scratch = sample ? at<void>(ws, L.samp) : nullptr;
+                     hipStream_t st, Rec* surv_rec = nullptr, Rec* cand = nullptr) {
+  const bool fused = surv_rec && n >= kSampleMin;
+  SamplePoly* poly = fused ? at<SamplePoly>(ws, L.poly) : nullptr;
+  void* scratch = fused ? at<void>(ws, L.samp) : nullptr;
   const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
   Header* hdr = at<Header>(ws, L.hdr);
   Result* res = at<Result>(ws, L.res);
   const uint32_t g1 = reduce_blocks(n, ctx->reduce_max_blocks);
   const uint32_t g2 = filter_blocks(n, ctx->filter_max_blocks);
+  double* partials = at<double>(ws, L.partials);
+  uint32_t* part_bad = at<uint32_t>(ws, L.part_bad);
   hipError_t e;
-  {
+  if (fused) {
+    {
+      ProfScope p(ctx, st, "sample_poly");
+      e = launch_sample_poly(d_xy, n, scratch, poly, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "sample polygon launch");
+    {
+      ProfScope p(ctx, st, "pass_fused");
+      e = launch_pass_hull(d_xy, n, head, partials, part_bad, poly, cand, scratch, g1, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "fused pass launch");
+  } else {
     ProfScope p(ctx, st, "reduce8");
-    e = launch_reduce8(d_xy, n, head, at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad),
-                       scratch, g1, st);
+    e = launch_reduce8(d_xy, n, head, partials, part_bad, g1, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
   }
-  if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
   {
     ProfScope p(ctx, st, "oct_build");
-    e = launch_oct_build(at<double>(ws, L.partials), at<uint32_t>(ws, L.part_bad), g1, hdr, res,
-                         at<uint64_t>(ws, L.tstat), g2, d_xy, n, scratch, poly, st);
+    e = launch_oct_build(partials, part_bad, g1, hdr, res, at<uint64_t>(ws, L.tstat), g2, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
+  if (fused) {
+    ProfScope p(ctx, st, "cand_filter");
+    e = launch_cand_filter(cand, scratch, poly, hdr, surv_rec, count_out, &res->ncand,
+                           (uint32_t)ctx->cu_count * 4, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "candidate filter launch");
+  }
   {
     ProfScope p(ctx, st, "filter_compact");
     if (surv_rec)
@@ -498,7 +525,9 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
   Rec* srec = at<Rec>(d_ws, L.surv);
   Rec* rec[2] = {at<Rec>(d_ws, L.recA), at<Rec>(d_ws, L.recB)};
-  if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec))
+  // Candidates of the fused pass go to list B (first written again by round 1).
+  if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec,
+                               rec[1]))
     return s;
 
   const Result* hres = reinterpret_cast<const Result*>(ctx->pinned);
@@ -520,6 +549,10 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull final");
   prof_collect(ctx, st);
   if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
+  ch_hull_info info{};
+  info.n = n;
+  info.candidates = hres->ncand;
+  info.survivors = hres->cin;
   bool large = false;
   int round = 0;
   int last_list = -1;  // record list holding the latest round's output
@@ -610,6 +643,10 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
 
   const uint32_t h = hres->h;
   *h_out = h;
+  info.rounds = (uint32_t)round;
+  info.large_path = large ? 1u : 0u;
+  info.h = h;
+  ctx->last = info;
   if (h > cap) return fail(ctx, CH_E_CAPACITY, "hull has %u vertices, capacity %u", h, cap);
   if (h <= pin_n) {
     std::memcpy(h_hull_idx, hidx, size_t(h) * 4);
@@ -738,6 +775,12 @@ ch_status ch_tune_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, u
   if (best_out) *best_out = best;
   if (!ctx->tune_path.empty() && !save_tune_cache(ctx))
     return fail(ctx, CH_E_INVALID_ARG, "cannot write the tune cache %s", ctx->tune_path.c_str());
+  return CH_OK;
+}
+
+ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out) {
+  if (!ctx || !out) return CH_E_INVALID_ARG;
+  *out = ctx->last;
   return CH_OK;
 }
 

@@ -162,8 +162,10 @@ __device__ double box_scale_lane(const int64_t* vx, const int64_t* vy, int lane)
 }
 
 // One wave: decode the octagon from the slot keys, check the domain, write
-// the edge forms and the inscribed box to `o`, and reset vidx (may be null).
-// Lanes 0-7 decode one slot each; lanes 0-31 test one (edge, corner) pair each.
+// the edge forms and (BOX) the inscribed box to `o`, and reset vidx (may be
+// null). Lanes 0-7 decode one slot each; lanes 0-31 test one (edge, corner)
+// pair each.
+template <bool BOX = true>
 __device__ void octagon_wave(const Keys& k, Octagon& o, uint32_t* vidx, uint32_t dom_bad) {
   const int lane = threadIdx.x & 63;
   const double K[8] = {k.mxE, k.mxNE, k.mxN, k.mnSE, k.mnE, k.mnNE, k.mnN, k.mxSE};
@@ -194,6 +196,10 @@ __device__ void octagon_wave(const Keys& k, Octagon& o, uint32_t* vidx, uint32_t
     o.vx[lane] = (int32_t)mx;
     o.vy[lane] = (int32_t)my;
     if (vidx) vidx[lane] = 0xFFFFFFFFu;
+  }
+  if (!BOX) {
+    if (lane == 0) o.status = ok ? 0u : 1u;
+    return;
   }
   const double t0 = box_scale_lane(vx, vy, lane);
   bool box_ok = false;
@@ -245,6 +251,7 @@ __device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint
     res->status = RES_PENDING;
     res->h = 0;
     res->lcount = res->ucount = 0;
+    res->ncand = 0;
   }
   for (int r = lane; r < kMaxRounds; r += 64) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
   if (lane < 4) res->win_cnt[lane] = 0;
@@ -261,9 +268,7 @@ constexpr int kU = 4;
 
 __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
                                                     uint32_t head, double* __restrict__ partials,
-                                                    uint32_t* __restrict__ part_bad,
-                                                    SampleDirs* __restrict__ sd) {
-  if (sd && blockIdx.x == 0) sample_dirs_clear(sd);  // for the octagon build's sample blocks
+                                                    uint32_t* __restrict__ part_bad) {
   Keys k;
   keys_init(k);
   bool bad = false;
@@ -319,52 +324,43 @@ __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy
   }
 }
 
-// Workgroup 0: combine the pass-1 partials (all loads issued up front),
-// build the octagon, and reset every per-call counter and look-back word used
-// by the kernels that follow. On the hull path (sd != null) workgroups 1 ..
-// kSampleBlocks build the sample polygon of the refined filter meanwhile.
-__global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__ partials,
-                                                      const uint32_t* __restrict__ part_bad,
-                                                      uint32_t nparts, Header* __restrict__ hdr,
-                                                      Result* __restrict__ res,
-                                                      uint64_t* __restrict__ tstat,
-                                                      uint32_t ntstat,
-                                                      const float* __restrict__ xy, uint32_t n,
-                                                      SampleDirs* __restrict__ sd,
-                                                      SamplePoly* __restrict__ poly) {
-  if (blockIdx.x > 0) {
-    sample_dirs_block(xy, n, sd, poly, blockIdx.x - 1, gridDim.x - 1);
-    return;
-  }
+// Combines the pass-1 partials of nparts workgroups (all loads issued up
+// front). Every thread calls it; on return the keys are valid in every lane
+// of wave 0, and the domain flag in every thread.
+__device__ uint32_t combine_partials(const double* __restrict__ partials,
+                                     const uint32_t* __restrict__ part_bad, uint32_t nparts,
+                                     Keys& k) {
   constexpr int kPer = kReduceMaxBlocks / kBlock;
-  Keys k;
+  constexpr int kChunk = 4;  // partials in flight per thread (register budget)
   keys_init(k);
   uint32_t bad = 0;
-  double4 a[kPer][2];
-  uint32_t bb[kPer];
   const double4* __restrict__ p4 = reinterpret_cast<const double4*>(partials);
+  for (int r0 = 0; r0 < kPer; r0 += kChunk) {
+    if (threadIdx.x + r0 * kBlock >= nparts) break;
+    double4 a[kChunk][2];
+    uint32_t bb[kChunk];
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const uint32_t b = threadIdx.x + r * kBlock;
-    if (b < nparts) {
-      a[r][0] = p4[2 * b];
-      a[r][1] = p4[2 * b + 1];
-      bb[r] = part_bad[b];
+    for (int r = 0; r < kChunk; ++r) {
+      const uint32_t b = threadIdx.x + (r0 + r) * kBlock;
+      if (b < nparts) {
+        a[r][0] = p4[2 * b];
+        a[r][1] = p4[2 * b + 1];
+        bb[r] = part_bad[b];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      const uint32_t b = threadIdx.x + (r0 + r) * kBlock;
+      if (b < nparts) {
+        const double v[8] = {a[r][0].x, a[r][0].y, a[r][0].z, a[r][0].w,
+                             a[r][1].x, a[r][1].y, a[r][1].z, a[r][1].w};
+        Keys o;
+        keys_from_array(o, v);
+        keys_merge(k, o);
+        bad |= bb[r];
+      }
     }
   }
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const uint32_t b = threadIdx.x + r * kBlock;
-    if (b < nparts) {
-      const double v[8] = {a[r][0].x, a[r][0].y, a[r][0].z, a[r][0].w,
-                           a[r][1].x, a[r][1].y, a[r][1].z, a[r][1].w};
-      Keys o;
-      keys_from_array(o, v);
-      keys_merge(k, o);
-      bad |= bb[r];
-    }
-  }
-  for (uint32_t i = threadIdx.x; i < ntstat; i += blockDim.x) tstat[i] = 0ull;
   const uint64_t badmask = __ballot(bad != 0);
   __shared__ uint32_t s_bad;
   if (threadIdx.x == 0) s_bad = 0;
@@ -377,8 +373,22 @@ __global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = __shfl(v[i], 0);
     keys_from_array(k, v);
-    build_octagon_wave(k, hdr, res, s_bad);
   }
+  return s_bad;
+}
+
+// One workgroup: combine the pass-1 partials, build the octagon, and reset
+// every per-call counter and look-back word used by the kernels that follow.
+__global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__ partials,
+                                                      const uint32_t* __restrict__ part_bad,
+                                                      uint32_t nparts, Header* __restrict__ hdr,
+                                                      Result* __restrict__ res,
+                                                      uint64_t* __restrict__ tstat,
+                                                      uint32_t ntstat) {
+  Keys k;
+  const uint32_t bad = combine_partials(partials, part_bad, nparts, k);
+  for (uint32_t i = threadIdx.x; i < ntstat; i += blockDim.x) tstat[i] = 0ull;
+  if (threadIdx.x < 64) build_octagon_wave(k, hdr, res, bad);
 }
 
 // ---------------------------------------------------------------- pass 2
@@ -658,10 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   for (uint32_t i = kCapW + lane; i < cw; i += 64) surv[off + i] = staging[sbase + i];
 }
 
-// Pass 2 of the hull path. The hull pass sorts its candidates, so their order
-// is free: the grid walks the points exactly as pass 1 does (each wave takes
-// every nw-th batch of kU rows, next batch's loads issued before the current
-// one is tested), tests them (octagon box, sample-polygon disc, then the
+// Pass 2 of the hull path when there is no fused pass (fewer than kSampleMin
+// points, or no usable sample polygon). The hull pass sorts its candidates,
+// so their order is free: the grid walks the points exactly as pass 1 does
+// (each wave takes every nw-th batch of kU rows, next batch's loads issued
+// before the current one is tested), tests them (octagon box, then the
 // per-wave queue of exact tests), stages survivor records per wave in LDS and
 // flushes them to `surv` with one atomic reservation per flush -- no ordering
 // and no look-back. The head point and an odd last point go to workgroup 0.
@@ -669,10 +680,12 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
                                                         uint32_t head, Header* __restrict__ hdr,
                                                         Rec* __restrict__ surv,
                                                         uint32_t* __restrict__ count_out,
-                                                        const SamplePoly* __restrict__ poly) {
+                                                        const SamplePoly* __restrict__ gate) {
+  // After a fused pass with a usable sample polygon the candidates are
+  // filtered by k_cand_filter instead, and this pass has nothing to do.
+  if (gate && gate->nv >= 3) return;
   constexpr int kCapW = StageCap<Rec>::value;
   __shared__ Rec s_buf[kWaves][kCapW];
-  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
   const Octagon* __restrict__ o = &hdr->oct;
@@ -683,16 +696,6 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
     return;
   }
-  const uint32_t pnv = poly ? min(poly->nv, (uint32_t)kPolyMax) : 0u;
-  const bool use_sp = pnv >= 3;
-  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
-  if (use_sp) {
-    for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
-    pcx = (float)poly->cx * (1.0f / kGridF);
-    pcy = (float)poly->cy * (1.0f / kGridF);
-    pr2 = poly->r2;
-  }
-  __syncthreads();
   const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
 
   uint32_t cw = 0, qn = 0;  // staged survivors, queued points (wave-uniform)
@@ -705,10 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
     cw = 0;
   };
   auto exact_keep = [&](float x, float y, uint32_t g) {
-    bool keep = classify<false>(x, y, g, o, vidx).keep;
-    if (keep && use_sp)
-      keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
-    return keep;
+    return classify<false>(x, y, g, o, vidx).keep;
   };
   auto drain = [&](uint32_t base, uint32_t cnt) {
     float x = 0.f, y = 0.f;
@@ -740,12 +740,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
     const uint32_t g = head + 2 * q;
     const bool in0 = (v.x > bxl) & (v.x < bxh) & (v.y > byl) & (v.y < byh);
     const bool in1 = (v.z > bxl) & (v.z < bxh) & (v.w > byl) & (v.w < byh);
-    bool t0 = val & !in0, t1 = val & !in1;
+    const bool t0 = val & !in0, t1 = val & !in1;
     if (__ballot(t0 | t1)) {
-      if (use_sp) {
-        t0 = t0 && !in_disc(v.x, v.y, pcx, pcy, pr2);
-        t1 = t1 && !in_disc(v.z, v.w, pcx, pcy, pr2);
-      }
       push(t0, v.x, v.y, g);
       push(t1, v.z, v.w, g + 1);
     }
@@ -799,6 +795,199 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
       const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
       if (exact_keep(x, y, g)) surv[atomicAdd(count_out, 1u)] = make_payload<Rec>(g, x, y);
     }
+  }
+}
+
+// Hull path from kSampleMin points, with the sample polygon built first: one
+// read of the points does pass 1 -- the exact 8-way extremes, per-workgroup
+// partials and the domain flag, as k_reduce8 -- and in the same pass keeps the
+// points not strictly inside the sample polygon as candidate records (disc
+// test, then the exact fan test through the per-wave queue). The octagon test
+// then runs on the candidates alone (k_cand_filter): every point it would
+// keep is either a candidate or strictly inside a polygon of input points,
+// which no hull vertex is. Without a usable polygon this is pass 1 only, and
+// k_filter_hull makes the second read.
+__global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ xy, uint32_t n,
+                                                      uint32_t head, double* __restrict__ partials,
+                                                      uint32_t* __restrict__ part_bad,
+                                                      const SamplePoly* __restrict__ poly,
+                                                      Rec* __restrict__ cand,
+                                                      uint32_t* __restrict__ cand_count) {
+  constexpr int kCapW = StageCap<Rec>::value;
+  __shared__ Rec s_buf[kWaves][kCapW];
+  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
+  __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
+  __shared__ uint32_t s_qg[kWaves][kQueue];
+  __shared__ uint32_t s_bad;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t pnv = min(poly->nv, (uint32_t)kPolyMax);
+  const bool use_sp = pnv >= 3;
+  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+  if (use_sp) {
+    for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
+    pcx = (float)poly->cx * (1.0f / kGridF);
+    pcy = (float)poly->cy * (1.0f / kGridF);
+    pr2 = poly->r2;
+  }
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+
+  Keys k;
+  keys_init(k);
+  bool bad = false;
+  uint32_t cw = 0, qn = 0;  // staged candidates, queued points (wave-uniform)
+  auto flush = [&]() {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(cand_count, cw);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < cw; i += 64) cand[base + i] = s_buf[w][i];
+    wave_sync();
+    cw = 0;
+  };
+  auto outside = [&](float x, float y) {
+    return !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+  };
+  auto drain = [&](uint32_t base, uint32_t cnt) {
+    float x = 0.f, y = 0.f;
+    uint32_t g = 0;
+    if (lane < (int)cnt) { x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; g = s_qg[w][base + lane]; }
+    wave_sync();
+    const bool keep = lane < (int)cnt && outside(x, y);
+    const uint64_t b = __ballot(keep);
+    if (!b) return;
+    if (cw + popc64(b) > (uint32_t)kCapW) flush();
+    if (keep) s_buf[w][cw + popc64(b & lt)] = make_payload<Rec>(g, x, y);
+    cw += popc64(b);
+  };
+  auto push = [&](bool q, float x, float y, uint32_t g) {
+    const uint64_t m = __ballot(q);
+    if (!m) return;
+    if (q) {
+      const uint32_t pos = qn + popc64(m & lt);
+      s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = g;
+    }
+    qn += popc64(m);
+    wave_sync();
+    if (qn >= 64) {
+      qn -= 64;
+      drain(qn, 64);
+    }
+  };
+
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
+  const uint32_t nfull = (n - head) >> 1;
+  const uint32_t gw = blockIdx.x * kWaves + w;
+  const uint32_t nw = gridDim.x * kWaves;
+  const uint32_t per_batch = kU * 64;
+  const uint32_t nbatch = (nfull + per_batch - 1) / per_batch;
+  if (gw < nbatch) {
+    float4 cur[kU], nxt[kU];
+    uint32_t b = gw;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t q = b * per_batch + u * 64 + lane;
+      cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+    }
+    while (true) {
+      const uint32_t bn = b + nw;
+      const bool more = bn < nbatch;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t q = bn * per_batch + u * 64 + lane;
+          nxt[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        // Lanes past the end hold a copy of the last pair: harmless for the
+        // extremes, excluded from the candidates.
+        keys_add(k, cur[u].x, cur[u].y, bad);
+        keys_add(k, cur[u].z, cur[u].w, bad);
+      }
+      if (use_sp) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t q = b * per_batch + u * 64 + lane;
+          const bool val = q < nfull;
+          const float4 v = cur[u];
+          const bool t0 = val && !in_disc(v.x, v.y, pcx, pcy, pr2);
+          const bool t1 = val && !in_disc(v.z, v.w, pcx, pcy, pr2);
+          if (__ballot(t0 | t1)) {
+            const uint32_t g = head + 2 * q;
+            push(t0, v.x, v.y, g);
+            push(t1, v.z, v.w, g + 1);
+          }
+        }
+      }
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+      b = bn;
+    }
+  }
+  if (use_sp) {
+    if (qn) drain(0, qn);
+    if (cw) flush();
+  }
+  // The head point (xy 8 mod 16 bytes aligned) and an odd last point.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    uint32_t single[2];
+    int ns = 0;
+    if (head) single[ns++] = 0;
+    if ((n - head) & 1) single[ns++] = n - 1;
+    for (int i = 0; i < ns; ++i) {
+      const uint32_t g = single[i];
+      const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
+      keys_add(k, x, y, bad);
+      if (use_sp && outside(x, y)) cand[atomicAdd(cand_count, 1u)] = make_payload<Rec>(g, x, y);
+    }
+  }
+  const uint64_t badmask = __ballot(bad);
+  if (lane == 0 && badmask) s_bad = 1;
+  block_keys(k);
+  if (threadIdx.x == 0) {
+    keys_to_array(k, partials + size_t(blockIdx.x) * 8);
+    part_bad[blockIdx.x] = s_bad;
+  }
+}
+
+// The octagon test (Alg. 1/2 with Sec. I's boundary rule) on the fused
+// pass's candidate records; survivors are appended to `surv` (one atomic per
+// wave and 64 candidates). Idle when the fused pass had no polygon.
+__global__ __launch_bounds__(kBlock) void k_cand_filter(const Rec* __restrict__ cand,
+                                                        const uint32_t* __restrict__ cand_count,
+                                                        const SamplePoly* __restrict__ gate,
+                                                        Header* __restrict__ hdr,
+                                                        Rec* __restrict__ surv,
+                                                        uint32_t* __restrict__ count_out,
+                                                        uint32_t* __restrict__ ncand_out) {
+  if (gate->nv < 3) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ncand_out = *cand_count;
+  const Octagon* __restrict__ o = &hdr->oct;
+  if (o->status != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t m = *cand_count;
+  for (uint32_t base = (blockIdx.x * kWaves + w) * 64; base < m; base += gridDim.x * kBlock) {
+    const uint32_t i = base + lane;
+    Rec r{};
+    bool keep = false;
+    if (i < m) {
+      r = cand[i];
+      keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
+                             hdr->vidx).keep;
+    }
+    const uint64_t b = __ballot(keep);
+    if (!b) continue;
+    uint32_t pos = 0;
+    if (lane == 0) pos = atomicAdd(count_out, popc64(b));
+    pos = __shfl(pos, 0);
+    if (keep) surv[pos + popc64(b & lt)] = r;
   }
 }
 
@@ -1101,21 +1290,33 @@ uint32_t filter_blocks(uint32_t n, uint32_t max_blocks) {
 }
 
 hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* partials,
-                          uint32_t* part_bad, void* sample_scratch, uint32_t blocks,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad,
-                     static_cast<SampleDirs*>(sample_scratch));
+                          uint32_t* part_bad, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce8, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad);
   return hipGetLastError();
 }
 
-// sample_scratch / poly non-null: also build the sample polygon (n >= kSampleN).
 hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
-                            const float* xy, uint32_t n, void* sample_scratch, SamplePoly* poly,
                             hipStream_t st) {
-  const uint32_t grid = 1 + (sample_scratch ? kSampleBlocks : 0);
-  hipLaunchKernelGGL(k_oct_build, dim3(grid), dim3(kBlock), 0, st, partials, part_bad, nparts, hdr, res,
-                     tstat, ntstat, xy, n, static_cast<SampleDirs*>(sample_scratch), poly);
+  hipLaunchKernelGGL(k_oct_build, dim3(1), dim3(kBlock), 0, st, partials, part_bad, nparts, hdr, res,
+                     tstat, ntstat);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
+                            uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
+                            uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_pass_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad,
+                     poly, cand, &static_cast<SampleDirs*>(scratch)->cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_filter(const Rec* cand, const void* scratch, const SamplePoly* gate,
+                              Header* hdr, Rec* surv, uint32_t* count_out, uint32_t* ncand_out,
+                              uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_cand_filter, dim3(blocks), dim3(kBlock), 0, st, cand,
+                     &static_cast<const SampleDirs*>(scratch)->cand, gate, hdr, surv, count_out,
+                     ncand_out);
   return hipGetLastError();
 }
 
@@ -1133,9 +1334,9 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
 
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             const SamplePoly* poly, hipStream_t st) {
+                             const SamplePoly* gate, hipStream_t st) {
   hipLaunchKernelGGL(k_filter_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, surv,
-                     count_out, poly);
+                     count_out, gate);
   return hipGetLastError();
 }
 
@@ -1149,8 +1350,8 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 namespace chk {
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, uint32_t nsets,
-                               const BatchHdr* bh, SamplePoly* polys, uint32_t sample_min,
-                               uint32_t grid, hipStream_t st);
+                               const BatchHdr* bh, const SetState* sets, SamplePoly* polys,
+                               uint32_t sample_min, uint32_t grid, hipStream_t st);
 
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
@@ -1159,11 +1360,11 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     hipStream_t st) {
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
                      sets, tiles);
-  hipError_t e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(kBlock), 0, st, xy, bh, tiles, sets);
   hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
                      nsets, bh, sets);
+  hipError_t e = launch_batch_sample(xy, off, nsets, bh, sets, polys, sample_min, sample_grid, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_filter, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets,
                      polys, recs);
   return hipGetLastError();

@@ -179,60 +179,94 @@ __device__ __forceinline__ void dir_max2(const int2* __restrict__ sp, uint32_t c
   }
 }
 
-// Single set: the direction maxima live in the workspace. Block 0 of pass 1
-// clears them (sample_dirs_clear); during the octagon build, extra
-// workgroups each take sample points b*kSamplePer .. +kSamplePer-1 of kSampleN
-// spread evenly over [0, n) (point floor(k n / kSampleN)), fold their maximum
-// per direction into the shared maxima (64-bit atomic max of the biased dot
-// product above the sample number), and the last one to arrive builds the
-// polygon from them (sample_dirs_block).
+// Single set: the direction maxima live in the workspace and are cleared
+// first (sample_dirs_clear). Then each workgroup takes sample points
+// b*kSamplePer .. +kSamplePer-1 of kSampleN spread evenly over [0, n) (point
+// floor(k n / kSampleN)) -- all of them, or with an octagon `oct` only those
+// strictly outside it (any input points span a safe polygon) -- folds their
+// maximum per direction into the shared maxima (64-bit atomic max of the
+// biased dot product above the sample number), and the last one to arrive
+// builds the polygon from them, or leaves it out when some direction got no
+// point (sample_dirs_block).
 struct SampleDirs {
   uint64_t key[kPolyMax];
   uint32_t arrive;
-  uint32_t pad[63];
+  uint32_t cand;       // candidate records written by the fused pass
+  uint32_t pad[62];
 };
 static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256, "workspace slot of the maxima");
 
 __device__ __forceinline__ void sample_dirs_clear(SampleDirs* __restrict__ sd) {
   for (uint32_t d = threadIdx.x; d < (uint32_t)kPolyMax; d += kBlock) sd->key[d] = 0ull;
-  if (threadIdx.x == 0) sd->arrive = 0;
+  if (threadIdx.x == 0) {
+    sd->arrive = 0;
+    sd->cand = 0;
+  }
 }
 
 __device__ inline void sample_dirs_block(const float* __restrict__ xy, uint32_t n,
-                                  SampleDirs* __restrict__ sd, SamplePoly* __restrict__ poly,
-                                  uint32_t blk, uint32_t nblk) {
+                                         const Octagon* __restrict__ oct,
+                                         SampleDirs* __restrict__ sd, SamplePoly* __restrict__ poly,
+                                         uint32_t blk, uint32_t nblk) {
   static_assert(kPolyMax == 2 * kBlock, "two directions per thread");
+  static_assert(kSamplePer == (uint32_t)kBlock, "one sample point per thread");
   __shared__ int2 sp[kSamplePer];
+  __shared__ uint32_t sq[kSamplePer];
   __shared__ int32_t px[kPolyMax], py[kPolyMax];
-  __shared__ uint32_t s_last;
-  for (uint32_t q = threadIdx.x; q < kSamplePer; q += kBlock) {
-    const uint32_t k = blk * kSamplePer + q;
-    sp[q] = grid_point(xy, (size_t)((uint64_t(k) * n) / kSampleN));
+  __shared__ uint32_t s_last, s_miss;
+  // This thread's sample point; kept when strictly outside the octagon.
+  const uint32_t k = blk * kSamplePer + threadIdx.x;
+  const int2 p = grid_point(xy, (size_t)((uint64_t(k) * n) / kSampleN));
+  bool out = oct == nullptr;
+  if (oct && oct->status == 0) {
+    const double x = (double)p.x * 0x1p-20, y = (double)p.y * 0x1p-20;
+    double mn = __builtin_inf();
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      mn = __builtin_fmin(mn, __builtin_fma(oct->A[i], x, __builtin_fma(oct->B[i], y, oct->C[i])));
+    out = mn < 0.0;
   }
+  uint32_t m;
+  const uint32_t pos = block_excl_scan(out ? 1u : 0u, m);
+  if (out) { sp[pos] = p; sq[pos] = k; }
   __syncthreads();
-  const uint32_t d = threadIdx.x;
-  int32_t a0, b0, a1, b1;
-  direction(d, kPolyMax, a0, b0);
-  direction(d + kBlock, kPolyMax, a1, b1);
-  int32_t e0, e1;
-  uint32_t q0, q1;
-  dir_max2(sp, kSamplePer, a0, b0, a1, b1, e0, q0, e1, q1);
-  const uint32_t k0 = blk * kSamplePer;
-  atomicMax((unsigned long long*)&sd->key[d], (unsigned long long)dir_key(e0, k0 + q0));
-  atomicMax((unsigned long long*)&sd->key[d + kBlock], (unsigned long long)dir_key(e1, k0 + q1));
+  if (m) {
+    const uint32_t d = threadIdx.x;
+    int32_t a0, b0, a1, b1;
+    direction(d, kPolyMax, a0, b0);
+    direction(d + kBlock, kPolyMax, a1, b1);
+    int32_t e0, e1;
+    uint32_t q0, q1;
+    dir_max2(sp, m, a0, b0, a1, b1, e0, q0, e1, q1);
+    atomicMax((unsigned long long*)&sd->key[d], (unsigned long long)dir_key(e0, sq[q0]));
+    atomicMax((unsigned long long*)&sd->key[d + kBlock], (unsigned long long)dir_key(e1, sq[q1]));
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     s_last = atomicAdd(&sd->arrive, 1u) == nblk - 1 ? 1u : 0u;
+    s_miss = 0;
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  for (uint32_t e = threadIdx.x; e < (uint32_t)kPolyMax; e += kBlock) {
-    const uint64_t key = __hip_atomic_load(&sd->key[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int2 p = grid_point(xy, (size_t)((uint64_t((uint32_t)key) * n) / kSampleN));
-    px[e] = p.x;
-    py[e] = p.y;
+  uint64_t key[kPolyMax / kBlock];
+#pragma unroll
+  for (int e = 0; e < kPolyMax / kBlock; ++e) {
+    key[e] = __hip_atomic_load(&sd->key[threadIdx.x + e * kBlock], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    if (!key[e]) s_miss = 1;  // a direction without a sample point outside the octagon
+  }
+  __syncthreads();
+  if (s_miss) {
+    if (threadIdx.x == 0) poly->nv = 0;
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < kPolyMax / kBlock; ++e) {
+    const int2 v = grid_point(xy, (size_t)((uint64_t((uint32_t)key[e]) * n) / kSampleN));
+    px[threadIdx.x + e * kBlock] = v.x;
+    py[threadIdx.x + e * kBlock] = v.y;
   }
   __syncthreads();
   build_poly(px, py, kPolyMax, poly);

@@ -132,3 +132,21 @@ def test_batch_refined(ctx):
         want = oracle.hull(s)
         assert cnt[k] == len(want), k
         assert np.array_equal(idx[off[k]: off[k] + cnt[k]], want), k
+
+
+def test_fused_path_counts(ctx):
+    """The single-read path is taken from 2^17 points and keeps few
+    candidates on ring data; below that size, or with a degenerate sample,
+    the two-read path runs (no candidates). Hulls match the oracle."""
+    _say("refined fused-path counts")
+    ring = workloads.annulus(SAMPLE_MIN + 100, 93, 0.49, 0.5)
+    assert np.array_equal(ctx.hull(_dev(ring)), oracle.hull(ring))
+    info = ctx.last_hull_info()
+    assert info["n"] == ring.shape[0] and 0 < info["candidates"] < ring.shape[0] // 10
+    assert info["survivors"] <= info["candidates"]
+    small = workloads.annulus(SAMPLE_MIN - 1, 94, 0.49, 0.5)
+    assert np.array_equal(ctx.hull(_dev(small)), oracle.hull(small))
+    assert ctx.last_hull_info()["candidates"] == 0
+    line = _cases(SAMPLE_MIN)["collinear"]
+    assert np.array_equal(ctx.hull(_dev(line)), oracle.hull(line))
+    assert ctx.last_hull_info()["candidates"] == 0
