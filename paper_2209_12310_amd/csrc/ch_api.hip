@@ -31,16 +31,14 @@ hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, Sample
 hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
                             uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
                             uint32_t blocks, hipStream_t st);
-hipError_t launch_cand_filter(const Rec* cand, const void* scratch, const SamplePoly* gate,
-                              Header* hdr, Rec* surv, uint32_t* count_out, uint32_t* ncand_out,
-                              uint32_t blocks, hipStream_t st);
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
                          uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
                          uint32_t* staging, hipStream_t st);
 hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             const SamplePoly* gate, hipStream_t st);
+                             const SamplePoly* gate, const Rec* cand, const void* scratch,
+                             uint32_t* ncand_out, hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -239,16 +237,11 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
     e = launch_oct_build(partials, part_bad, g1, hdr, res, at<uint64_t>(ws, L.tstat), g2, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
-  if (fused) {
-    ProfScope p(ctx, st, "cand_filter");
-    e = launch_cand_filter(cand, scratch, poly, hdr, surv_rec, count_out, &res->ncand,
-                           (uint32_t)ctx->cu_count * 4, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "candidate filter launch");
-  }
   {
-    ProfScope p(ctx, st, "filter_compact");
+    ProfScope p(ctx, st, fused ? "cand_filter" : "filter_compact");
     if (surv_rec)
-      e = launch_filter_rec(d_xy, n, head, hdr, g1, surv_rec, count_out, poly, st);
+      e = launch_filter_rec(d_xy, n, head, hdr, g1, surv_rec, count_out, poly, cand, scratch,
+                            &res->ncand, st);
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);

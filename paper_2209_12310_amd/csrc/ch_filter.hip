@@ -24,6 +24,12 @@ namespace chk {
 
 static constexpr double kShift = 4194304.0;  // 2^22: primary key weight
 
+// Waits for every outstanding memory operation. Called once after a streaming
+// loop's first batch of loads: without it the wait-count insertion treats the
+// loop-carried current batch as possibly still in flight at the loop head and
+// waits for the prefetched batch too, which serialises the pipeline.
+__device__ __forceinline__ void wait_all_loads() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Streaming loads of two points (16 B) that bypass cache retention: the
 // points are read once per pass.
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -287,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy
       const uint32_t q = b * per_batch + u * 64 + lane;
       cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
     }
+    wait_all_loads();
     while (true) {
       const uint32_t bn = b + nw;
       const bool more = bn < nbatch;
@@ -552,6 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   if (r < r1) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) load_row(r + u < r1 ? r + u : r1 - 1, cur[u]);
+    wait_all_loads();
   }
   while (r < r1) {
     const uint32_t rn = r + kU;
@@ -668,6 +676,40 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
   for (uint32_t i = kCapW + lane; i < cw; i += 64) surv[off + i] = staging[sbase + i];
 }
 
+// The octagon test (Alg. 1/2 with Sec. I's boundary rule) on the fused
+// pass's candidate records; survivors are appended to `surv` (one atomic per
+// wave and 64 candidates). Run by k_filter_hull's grid after a fused pass
+// with a usable sample polygon.
+__device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __restrict__ cand_count,
+                            Header* __restrict__ hdr, Rec* __restrict__ surv,
+                            uint32_t* __restrict__ count_out, uint32_t* __restrict__ ncand_out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ncand_out = *cand_count;
+  const Octagon* __restrict__ o = &hdr->oct;
+  if (o->status != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t m = *cand_count;
+  for (uint32_t base = (blockIdx.x * kWaves + w) * 64; base < m; base += gridDim.x * kBlock) {
+    const uint32_t i = base + lane;
+    Rec r{};
+    bool keep = false;
+    if (i < m) {
+      r = cand[i];
+      keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
+                             hdr->vidx).keep;
+    }
+    const uint64_t b = __ballot(keep);
+    if (!b) continue;
+    uint32_t pos = 0;
+    if (lane == 0) pos = atomicAdd(count_out, popc64(b));
+    pos = __shfl(pos, 0);
+    if (keep) surv[pos + popc64(b & lt)] = r;
+  }
+}
+
 // Pass 2 of the hull path when there is no fused pass (fewer than kSampleMin
 // points, or no usable sample polygon). The hull pass sorts its candidates,
 // so their order is free: the grid walks the points exactly as pass 1 does
@@ -680,10 +722,16 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
                                                         uint32_t head, Header* __restrict__ hdr,
                                                         Rec* __restrict__ surv,
                                                         uint32_t* __restrict__ count_out,
-                                                        const SamplePoly* __restrict__ gate) {
-  // After a fused pass with a usable sample polygon the candidates are
-  // filtered by k_cand_filter instead, and this pass has nothing to do.
-  if (gate && gate->nv >= 3) return;
+                                                        const SamplePoly* __restrict__ gate,
+                                                        const Rec* __restrict__ cand,
+                                                        const uint32_t* __restrict__ cand_count,
+                                                        uint32_t* __restrict__ ncand_out) {
+  // After a fused pass with a usable sample polygon only its candidates need
+  // the octagon test; otherwise this is the second read of the points.
+  if (gate && gate->nv >= 3) {
+    cand_filter(cand, cand_count, hdr, surv, count_out, ncand_out);
+    return;
+  }
   constexpr int kCapW = StageCap<Rec>::value;
   __shared__ Rec s_buf[kWaves][kCapW];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
@@ -761,6 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
       const uint32_t q = b * per_batch + u * 64 + lane;
       cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
     }
+    wait_all_loads();
     while (true) {
       const uint32_t bn = b + nw;
       const bool more = bn < nbatch;
@@ -803,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
 // partials and the domain flag, as k_reduce8 -- and in the same pass keeps the
 // points not strictly inside the sample polygon as candidate records (disc
 // test, then the exact fan test through the per-wave queue). The octagon test
-// then runs on the candidates alone (k_cand_filter): every point it would
+// then runs on the candidates alone (cand_filter): every point it would
 // keep is either a candidate or strictly inside a polygon of input points,
 // which no hull vertex is. Without a usable polygon this is pass 1 only, and
 // k_filter_hull makes the second read.
@@ -889,6 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
       const uint32_t q = b * per_batch + u * 64 + lane;
       cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
     }
+    wait_all_loads();
     while (true) {
       const uint32_t bn = b + nw;
       const bool more = bn < nbatch;
@@ -907,17 +957,23 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
         keys_add(k, cur[u].z, cur[u].w, bad);
       }
       if (use_sp) {
+        // Disc tests of the whole batch first, then one branch per batch:
+        // a branch on each row's vote stalls the wave on every row.
+        uint32_t tm = 0;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const uint32_t q = b * per_batch + u * 64 + lane;
           const bool val = q < nfull;
           const float4 v = cur[u];
-          const bool t0 = val && !in_disc(v.x, v.y, pcx, pcy, pr2);
-          const bool t1 = val && !in_disc(v.z, v.w, pcx, pcy, pr2);
-          if (__ballot(t0 | t1)) {
-            const uint32_t g = head + 2 * q;
-            push(t0, v.x, v.y, g);
-            push(t1, v.z, v.w, g + 1);
+          tm |= (val & !in_disc(v.x, v.y, pcx, pcy, pr2)) ? 1u << (2 * u) : 0u;
+          tm |= (val & !in_disc(v.z, v.w, pcx, pcy, pr2)) ? 2u << (2 * u) : 0u;
+        }
+        if (__ballot(tm != 0)) {
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const uint32_t g = head + 2 * (b * per_batch + u * 64 + lane);
+            push((tm >> (2 * u)) & 1u, cur[u].x, cur[u].y, g);
+            push((tm >> (2 * u)) & 2u, cur[u].z, cur[u].w, g + 1);
           }
         }
       }
@@ -950,44 +1006,6 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
   if (threadIdx.x == 0) {
     keys_to_array(k, partials + size_t(blockIdx.x) * 8);
     part_bad[blockIdx.x] = s_bad;
-  }
-}
-
-// The octagon test (Alg. 1/2 with Sec. I's boundary rule) on the fused
-// pass's candidate records; survivors are appended to `surv` (one atomic per
-// wave and 64 candidates). Idle when the fused pass had no polygon.
-__global__ __launch_bounds__(kBlock) void k_cand_filter(const Rec* __restrict__ cand,
-                                                        const uint32_t* __restrict__ cand_count,
-                                                        const SamplePoly* __restrict__ gate,
-                                                        Header* __restrict__ hdr,
-                                                        Rec* __restrict__ surv,
-                                                        uint32_t* __restrict__ count_out,
-                                                        uint32_t* __restrict__ ncand_out) {
-  if (gate->nv < 3) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ncand_out = *cand_count;
-  const Octagon* __restrict__ o = &hdr->oct;
-  if (o->status != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
-    return;
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
-  const uint32_t m = *cand_count;
-  for (uint32_t base = (blockIdx.x * kWaves + w) * 64; base < m; base += gridDim.x * kBlock) {
-    const uint32_t i = base + lane;
-    Rec r{};
-    bool keep = false;
-    if (i < m) {
-      r = cand[i];
-      keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
-                             hdr->vidx).keep;
-    }
-    const uint64_t b = __ballot(keep);
-    if (!b) continue;
-    uint32_t pos = 0;
-    if (lane == 0) pos = atomicAdd(count_out, popc64(b));
-    pos = __shfl(pos, 0);
-    if (keep) surv[pos + popc64(b & lt)] = r;
   }
 }
 
@@ -1233,8 +1251,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
       if (__ballot(need0 | need1)) {
         bool t0 = need0, t1 = need1;
         if (use_sp) {
-          t0 = t0 && !in_disc(v.x, v.y, pcx, pcy, pr2);
-          t1 = t1 && !in_disc(v.z, v.w, pcx, pcy, pr2);
+          t0 = t0 & !in_disc(v.x, v.y, pcx, pcy, pr2);
+          t1 = t1 & !in_disc(v.z, v.w, pcx, pcy, pr2);
         }
         push(t0, v.x, v.y, g - base);
         push(t1, v.z, v.w, g + 1 - base);
@@ -1311,14 +1329,7 @@ hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_cand_filter(const Rec* cand, const void* scratch, const SamplePoly* gate,
-                              Header* hdr, Rec* surv, uint32_t* count_out, uint32_t* ncand_out,
-                              uint32_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_cand_filter, dim3(blocks), dim3(kBlock), 0, st, cand,
-                     &static_cast<const SampleDirs*>(scratch)->cand, gate, hdr, surv, count_out,
-                     ncand_out);
-  return hipGetLastError();
-}
+
 
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
                          uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
@@ -1332,11 +1343,14 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
   return hipGetLastError();
 }
 
+// gate/cand/scratch non-null: after a fused pass (see k_filter_hull).
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
-                             const SamplePoly* gate, hipStream_t st) {
+                             const SamplePoly* gate, const Rec* cand, const void* scratch,
+                             uint32_t* ncand_out, hipStream_t st) {
+  const uint32_t* cc = scratch ? &static_cast<const SampleDirs*>(scratch)->cand : nullptr;
   hipLaunchKernelGGL(k_filter_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, surv,
-                     count_out, gate);
+                     count_out, gate, cand, cc, ncand_out);
   return hipGetLastError();
 }
 

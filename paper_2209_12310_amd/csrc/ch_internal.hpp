@@ -145,7 +145,7 @@ inline Layout layout(uint32_t n) {
   L.wcnt = o;      o = align_up(o + 2 * (chain_cap / kHullTile + 4) * 4, 256);
   // Refined filter: the sample polygon and the direction maxima.
   L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
-  L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256, 256);
+  L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kSampleBlocks) * kPolyMax * 16, 256);
   L.total = o;
   return L;
 }

@@ -16,14 +16,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
                                                          const SetState* __restrict__ sets,
                                                          SamplePoly* __restrict__ polys,
                                                          uint32_t sample_min) {
-  static_assert(kBatchDirs == 2 * (uint32_t)kBlock, "two directions per thread");
+  static_assert(kBatchDirs == 2 * (uint32_t)kBlock, "a direction and its opposite per thread");
   constexpr uint32_t E = kBatchSample / kBlock;  // sample points per thread
   __shared__ int2 sp[kBatchSample];
   __shared__ int32_t px[kBatchDirs], py[kBatchDirs];
   const bool bad_off = bh->bad_offsets != 0;
-  int32_t a0, b0, a1, b1;
+  int32_t a0, b0;
   direction(threadIdx.x, kBatchDirs, a0, b0);
-  direction(threadIdx.x + kBlock, kBatchDirs, a1, b1);
   for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
     const uint64_t base = off[s];
     const uint64_t n = bad_off ? 0 : off[s + 1] - base;
@@ -57,9 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
       if (threadIdx.x == 0) polys[s].nv = 0;
       continue;
     }
-    int32_t e0, e1;
+    int32_t emax, emin;
     uint32_t q0, q1;
-    dir_max2(sp, m, a0, b0, a1, b1, e0, q0, e1, q1);
+    dir_minmax(sp, m, a0, b0, emax, q0, emin, q1);
     px[threadIdx.x] = sp[q0].x;
     py[threadIdx.x] = sp[q0].y;
     px[threadIdx.x + kBlock] = sp[q1].x;
@@ -69,23 +68,78 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
   }
 }
 
-// Single set, before the fused pass: clear the maxima, then kSampleBlocks
-// workgroups of sample_dirs_block over all sample points.
-__global__ __launch_bounds__(kBlock) void k_sample_zero(SampleDirs* __restrict__ sd) {
-  sample_dirs_clear(sd);
-}
+static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256 + size_t(kSampleBlocks) * kPolyMax * 16,
+              "workspace slot of the direction maxima");
 
 __global__ __launch_bounds__(kBlock) void k_sample_dirs(const float* __restrict__ xy, uint32_t n,
-                                                        SampleDirs* __restrict__ sd,
-                                                        SamplePoly* __restrict__ poly) {
-  sample_dirs_block(xy, n, nullptr, sd, poly, blockIdx.x, gridDim.x);
+                                                        SampleDirs* __restrict__ sd) {
+  static_assert(kPolyMax == 2 * kBlock, "a direction and its opposite per thread");
+  __shared__ int2 sp[kSamplePer];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sd->arrive = 0;  // for k_sample_reduce
+    sd->cand = 0;    // for the fused pass
+  }
+  const uint32_t k0 = blockIdx.x * kSamplePer;
+  for (uint32_t q = threadIdx.x; q < kSamplePer; q += kBlock)
+    sp[q] = grid_point(xy, (size_t)((uint64_t(k0 + q) * n) / kSampleN));
+  __syncthreads();
+  const uint32_t d = threadIdx.x;
+  int32_t a, b;
+  direction(d, kPolyMax, a, b);
+  int32_t emax, emin;
+  uint32_t qmax, qmin;
+  dir_minmax(sp, kSamplePer, a, b, emax, qmax, emin, qmin);
+  sd->part[blockIdx.x][d] = make_int4(emax, sp[qmax].x, sp[qmax].y, 0);
+  sd->part[blockIdx.x][d + kBlock] = make_int4(-emin, sp[qmin].x, sp[qmin].y, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sample_reduce(const float* __restrict__ xy, uint32_t n,
+                                                          SampleDirs* __restrict__ sd,
+                                                          SamplePoly* __restrict__ poly) {
+  constexpr uint32_t kLanes = kBlock / kReduceDirsPerBlock;  // lanes per direction
+  static_assert(kLanes == 32 && kSampleBlocks % kLanes == 0, "32 lanes per direction");
+  __shared__ int32_t px[kPolyMax], py[kPolyMax];
+  __shared__ uint32_t s_last;
+  const uint32_t d = blockIdx.x * kReduceDirsPerBlock + threadIdx.x / kLanes;
+  const uint32_t ln = threadIdx.x % kLanes;
+  // Each lane of a direction reads every kLanes-th row of the partials.
+  int4 best = make_int4(INT32_MIN, 0, 0, 0);
+#pragma unroll 8
+  for (uint32_t b = ln; b < kSampleBlocks; b += kLanes) {
+    const int4 v = sd->part[b][d];
+    best = v.x > best.x ? v : best;
+  }
+#pragma unroll
+  for (uint32_t o = 1; o < kLanes; o <<= 1) {
+    const int32_t ox = __shfl_xor(best.x, (int)o), oy = __shfl_xor(best.y, (int)o);
+    const int32_t oz = __shfl_xor(best.z, (int)o);
+    if (ox > best.x) { best.x = ox; best.y = oy; best.z = oz; }
+  }
+  if (ln == 0) {
+    sd->vx[d] = best.y;
+    sd->vy[d] = best.z;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&sd->arrive, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (uint32_t e = threadIdx.x; e < (uint32_t)kPolyMax; e += kBlock) {
+    px[e] = __hip_atomic_load(&sd->vx[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    py[e] = __hip_atomic_load(&sd->vy[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  build_poly(px, py, kPolyMax, poly);
 }
 
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
                               hipStream_t st) {
   SampleDirs* sd = static_cast<SampleDirs*>(scratch);
-  hipLaunchKernelGGL(k_sample_zero, dim3(1), dim3(kBlock), 0, st, sd);
-  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd, poly);
+  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd);
+  hipLaunchKernelGGL(k_sample_reduce, dim3(kSampleReduceBlocks), dim3(kBlock), 0, st, xy, n, sd, poly);
   return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@
 // hull is unchanged, only fewer candidates reach the hull pass.
 //
 // Directions: d = 0 .. D-1 counter-clockwise, (a, b) = round(1024 (cos, sin)
-// of 2 pi d / D). Their angles are strictly increasing (the rounding moves an
+// of 2 pi d / D) for d < D/2 and the negation of direction d - D/2 after
+// that (so one dot product serves a direction and its opposite). Their angles are strictly increasing (the rounding moves an
 // angle by < 1e-3 rad, the spacing is > 1e-2 rad), so the extreme points,
 // taken in direction order, run counter-clockwise around the sample's hull.
 // Dot products a x + b y of grid points stay below 1449 * 2^20 < 2^31.
@@ -26,9 +27,13 @@
 namespace chk {
 
 __device__ __forceinline__ void direction(uint32_t d, uint32_t D, int32_t& a, int32_t& b) {
-  const double t = 6.283185307179586 * (double)d / (double)D;
-  a = (int32_t)__builtin_rint(1024.0 * cos(t));
-  b = (int32_t)__builtin_rint(1024.0 * sin(t));
+  // Directions D/2 .. D-1 are the negations of 0 .. D/2-1, exactly.
+  const uint32_t h = d < D / 2 ? d : d - D / 2;
+  double sn, cs;
+  sincos(6.283185307179586 * (double)h / (double)D, &sn, &cs);
+  a = (int32_t)__builtin_rint(1024.0 * cs);
+  b = (int32_t)__builtin_rint(1024.0 * sn);
+  if (d >= D / 2) { a = -a; b = -b; }
 }
 
 // Grid coordinates of a point, clamped into the grid (see above).
@@ -154,122 +159,41 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
     for (uint32_t j = threadIdx.x; j < m; j += kBlock) { out->vx[j] = px[j]; out->vy[j] = py[j]; }
 }
 
-// Order-preserving key of a direction maximum: the dot product (biased to
-// unsigned; never 0 here) above the sample number.
-__device__ __forceinline__ uint64_t dir_key(int32_t dot, uint32_t tag) {
-  return ((uint64_t)((uint32_t)dot ^ 0x80000000u) << 32) | tag;
-}
-
-// Largest dot product over the sample points sp[0..cnt) (LDS) in the
-// directions (a0, b0) and (a1, b1), with the position of its first
-// occurrence. Every lane reads the same point (an LDS broadcast); the dot
+// Largest and smallest dot product over the sample points sp[0..cnt) (LDS)
+// in direction (a, b), with the positions of their first occurrences: the
+// maxima in the direction and in its opposite (whose dot product is the
+// negation). Every lane reads the same point (an LDS broadcast); the dot
 // products use 24-bit multiplies (|a|, |b| <= 1024, coordinates < 2^20).
-__device__ __forceinline__ void dir_max2(const int2* __restrict__ sp, uint32_t cnt, int32_t a0,
-                                         int32_t b0, int32_t a1, int32_t b1, int32_t& d0,
-                                         uint32_t& q0, int32_t& d1, uint32_t& q1) {
-  d0 = d1 = INT32_MIN;
-  q0 = q1 = 0;
+__device__ __forceinline__ void dir_minmax(const int2* __restrict__ sp, uint32_t cnt, int32_t a,
+                                           int32_t b, int32_t& dmax, uint32_t& qmax,
+                                           int32_t& dmin, uint32_t& qmin) {
+  dmax = INT32_MIN;
+  dmin = INT32_MAX;
+  qmax = qmin = 0;
 #pragma unroll 8
   for (uint32_t q = 0; q < cnt; ++q) {
     const int2 p = sp[q];
-    const int32_t e0 = __mul24(a0, p.x) + __mul24(b0, p.y);
-    const int32_t e1 = __mul24(a1, p.x) + __mul24(b1, p.y);
-    if (e0 > d0) { d0 = e0; q0 = q; }
-    if (e1 > d1) { d1 = e1; q1 = q; }
+    const int32_t e = __mul24(a, p.x) + __mul24(b, p.y);
+    if (e > dmax) { dmax = e; qmax = q; }
+    if (e < dmin) { dmin = e; qmin = q; }
   }
 }
 
-// Single set: the direction maxima live in the workspace and are cleared
-// first (sample_dirs_clear). Then each workgroup takes sample points
-// b*kSamplePer .. +kSamplePer-1 of kSampleN spread evenly over [0, n) (point
-// floor(k n / kSampleN)) -- all of them, or with an octagon `oct` only those
-// strictly outside it (any input points span a safe polygon) -- folds their
-// maximum per direction into the shared maxima (64-bit atomic max of the
-// biased dot product above the sample number), and the last one to arrive
-// builds the polygon from them, or leaves it out when some direction got no
-// point (sample_dirs_block).
+// Single set, before the fused pass. k_sample_dirs: workgroup b takes sample
+// points b*kSamplePer .. +kSamplePer-1 of kSampleN spread evenly over [0, n)
+// (point floor(k n / kSampleN)) and writes, per direction, its largest dot
+// product with that point's coordinates (one partial per workgroup and
+// direction, written contiguously, no atomics). k_sample_reduce: each
+// workgroup folds the partials of kReduceDirsPerBlock directions into the
+// extreme point per direction, and the last to arrive builds the polygon.
 struct SampleDirs {
-  uint64_t key[kPolyMax];
+  int32_t vx[kPolyMax], vy[kPolyMax];  // extreme sample point per direction
   uint32_t arrive;
   uint32_t cand;       // candidate records written by the fused pass
   uint32_t pad[62];
+  int4 part[kSampleBlocks][kPolyMax];  // (dot product, x, y, 0)
 };
-static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256, "workspace slot of the maxima");
-
-__device__ __forceinline__ void sample_dirs_clear(SampleDirs* __restrict__ sd) {
-  for (uint32_t d = threadIdx.x; d < (uint32_t)kPolyMax; d += kBlock) sd->key[d] = 0ull;
-  if (threadIdx.x == 0) {
-    sd->arrive = 0;
-    sd->cand = 0;
-  }
-}
-
-__device__ inline void sample_dirs_block(const float* __restrict__ xy, uint32_t n,
-                                         const Octagon* __restrict__ oct,
-                                         SampleDirs* __restrict__ sd, SamplePoly* __restrict__ poly,
-                                         uint32_t blk, uint32_t nblk) {
-  static_assert(kPolyMax == 2 * kBlock, "two directions per thread");
-  static_assert(kSamplePer == (uint32_t)kBlock, "one sample point per thread");
-  __shared__ int2 sp[kSamplePer];
-  __shared__ uint32_t sq[kSamplePer];
-  __shared__ int32_t px[kPolyMax], py[kPolyMax];
-  __shared__ uint32_t s_last, s_miss;
-  // This thread's sample point; kept when strictly outside the octagon.
-  const uint32_t k = blk * kSamplePer + threadIdx.x;
-  const int2 p = grid_point(xy, (size_t)((uint64_t(k) * n) / kSampleN));
-  bool out = oct == nullptr;
-  if (oct && oct->status == 0) {
-    const double x = (double)p.x * 0x1p-20, y = (double)p.y * 0x1p-20;
-    double mn = __builtin_inf();
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      mn = __builtin_fmin(mn, __builtin_fma(oct->A[i], x, __builtin_fma(oct->B[i], y, oct->C[i])));
-    out = mn < 0.0;
-  }
-  uint32_t m;
-  const uint32_t pos = block_excl_scan(out ? 1u : 0u, m);
-  if (out) { sp[pos] = p; sq[pos] = k; }
-  __syncthreads();
-  if (m) {
-    const uint32_t d = threadIdx.x;
-    int32_t a0, b0, a1, b1;
-    direction(d, kPolyMax, a0, b0);
-    direction(d + kBlock, kPolyMax, a1, b1);
-    int32_t e0, e1;
-    uint32_t q0, q1;
-    dir_max2(sp, m, a0, b0, a1, b1, e0, q0, e1, q1);
-    atomicMax((unsigned long long*)&sd->key[d], (unsigned long long)dir_key(e0, sq[q0]));
-    atomicMax((unsigned long long*)&sd->key[d + kBlock], (unsigned long long)dir_key(e1, sq[q1]));
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(&sd->arrive, 1u) == nblk - 1 ? 1u : 0u;
-    s_miss = 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  uint64_t key[kPolyMax / kBlock];
-#pragma unroll
-  for (int e = 0; e < kPolyMax / kBlock; ++e) {
-    key[e] = __hip_atomic_load(&sd->key[threadIdx.x + e * kBlock], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    if (!key[e]) s_miss = 1;  // a direction without a sample point outside the octagon
-  }
-  __syncthreads();
-  if (s_miss) {
-    if (threadIdx.x == 0) poly->nv = 0;
-    return;
-  }
-#pragma unroll
-  for (int e = 0; e < kPolyMax / kBlock; ++e) {
-    const int2 v = grid_point(xy, (size_t)((uint64_t((uint32_t)key[e]) * n) / kSampleN));
-    px[threadIdx.x + e * kBlock] = v.x;
-    py[threadIdx.x + e * kBlock] = v.y;
-  }
-  __syncthreads();
-  build_poly(px, py, kPolyMax, poly);
-}
+constexpr uint32_t kReduceDirsPerBlock = 8;
+constexpr uint32_t kSampleReduceBlocks = kPolyMax / kReduceDirsPerBlock;
 
 }  // namespace chk
