@@ -30,7 +30,7 @@ hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, Sample
                               hipStream_t st);
 hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
                             uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
-                            uint32_t blocks, hipStream_t st);
+                            uint32_t blocks, uint32_t narrow_blocks, hipStream_t st);
 hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr, uint64_t* tstat,
                          uint32_t blocks, uint32_t* surv, uint32_t* count_out, uint8_t* labels,
                          uint32_t* staging, hipStream_t st);
@@ -84,6 +84,8 @@ struct ch_ctx {
   int cu_count = 0;
   uint32_t reduce_max_blocks = 1024;  // persistent grid sizes, from the CU count
   uint32_t filter_max_blocks = 1024;
+  uint32_t fused_max_blocks = 768;
+  uint32_t narrow_blocks = 256;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   std::string err;
   ch_hull_info last{};  // counts of the last successful ch_hull
@@ -211,7 +213,7 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
   const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
   Header* hdr = at<Header>(ws, L.hdr);
   Result* res = at<Result>(ws, L.res);
-  const uint32_t g1 = reduce_blocks(n, ctx->reduce_max_blocks);
+  const uint32_t g1 = reduce_blocks(n, fused ? ctx->fused_max_blocks : ctx->reduce_max_blocks);
   const uint32_t g2 = filter_blocks(n, ctx->filter_max_blocks);
   double* partials = at<double>(ws, L.partials);
   uint32_t* part_bad = at<uint32_t>(ws, L.part_bad);
@@ -224,7 +226,8 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
     if (e != hipSuccess) return hip_fail(ctx, e, "sample polygon launch");
     {
       ProfScope p(ctx, st, "pass_fused");
-      e = launch_pass_hull(d_xy, n, head, partials, part_bad, poly, cand, scratch, g1, st);
+      e = launch_pass_hull(d_xy, n, head, partials, part_bad, poly, cand, scratch, g1,
+                           ctx->narrow_blocks, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "fused pass launch");
   } else {
@@ -418,6 +421,11 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
   if (ctx->reduce_max_blocks > (uint32_t)kReduceMaxBlocks) ctx->reduce_max_blocks = kReduceMaxBlocks;
   ctx->filter_max_blocks = (uint32_t)ctx->cu_count * 4;
   if (ctx->filter_max_blocks > (uint32_t)kFilterMaxBlocks) ctx->filter_max_blocks = kFilterMaxBlocks;
+  // The fused hull pass: three workgroups per CU when many points go to the
+  // exact test, one per CU (fewer, longer streams) when few do.
+  ctx->fused_max_blocks = (uint32_t)ctx->cu_count * 3;
+  if (ctx->fused_max_blocks > (uint32_t)kReduceMaxBlocks) ctx->fused_max_blocks = kReduceMaxBlocks;
+  ctx->narrow_blocks = (uint32_t)ctx->cu_count;
   // Overrides for tuning sweeps.
   if (const char* e = std::getenv("CH_REDUCE_BLOCKS")) {
     const long v = std::strtol(e, nullptr, 10);
@@ -426,6 +434,14 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
   if (const char* e = std::getenv("CH_FILTER_BLOCKS")) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1 && v <= kFilterMaxBlocks) ctx->filter_max_blocks = (uint32_t)v;
+  }
+  if (const char* e = std::getenv("CH_FUSED_BLOCKS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= kReduceMaxBlocks) ctx->fused_max_blocks = (uint32_t)v;
+  }
+  if (const char* e = std::getenv("CH_NARROW_BLOCKS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= kReduceMaxBlocks) ctx->narrow_blocks = (uint32_t)v;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kResBytes + 4 * kPinIdx,
                     hipHostMallocDefault) != hipSuccess) {

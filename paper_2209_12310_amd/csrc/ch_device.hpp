@@ -102,6 +102,17 @@ __device__ __forceinline__ bool in_disc(float x, float y, float cx, float cy, fl
   return __builtin_fmaf(dx, dx, dy * dy) < r2;
 }
 
+// The inner region of the polygon: its disc, or its octagon |dx| < os,
+// |dy| < os, |dx| + |dy| < ot about the same centre (also inside it; |dx|,
+// |dy| and their sum are exact for grid values, os and ot are verified
+// exactly). A point in either is strictly inside the polygon. Every
+// comparison is false for a NaN coordinate, so such a point is never inside.
+__device__ __forceinline__ bool in_inner(float x, float y, float cx, float cy, float r2, float os,
+                                         float ot) {
+  const float dx = __builtin_fabsf(x - cx), dy = __builtin_fabsf(y - cy);
+  return (__builtin_fmaf(dx, dx, dy * dy) < r2) | ((dx < os) & (dy < os) & (dx + dy < ot));
+}
+
 // Exact: p strictly inside the counter-clockwise strictly convex polygon
 // v[0..nv) (nv >= 3). p must lie strictly left of v0->v1 and strictly right
 // of v0->v[nv-1]; a binary search over the fan at v0 finds the wedge

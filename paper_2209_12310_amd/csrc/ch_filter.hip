@@ -271,6 +271,21 @@ __device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint
 // on its own and the float4 stream starts at point 1. Each block writes its 8
 // keys and a domain flag; k_oct_build combines them.
 constexpr int kU = 4;
+// Rows per batch of the fused hull pass, which runs with fewer workgroups
+// (it is launched with about one per CU: fewer, longer streams keep the
+// HBM reads closer together).
+constexpr int kUF = 8;
+// The fused pass runs on its whole grid when more than 1 in kWideRatio of
+// its estimate's points (kEstPer per thread) fall outside the polygon's
+// inner region.
+constexpr uint32_t kWideRatio = 300;
+constexpr uint32_t kEstPer = 4;
+
+// Compile-time mode passed to generic lambdas (one instantiation per mode).
+template <int M>
+struct IntC {
+  static constexpr int value = M;
+};
 
 __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
                                                     uint32_t head, double* __restrict__ partials,
@@ -476,11 +491,11 @@ template <class P>
 struct StageCap {
   static constexpr int value = 8192 / (int)sizeof(P);  // 8 KiB of LDS per wave
 };
-// Records (k_filter_hull) leave room for the sample polygon and the
-// exact-test queue within 40 KiB per workgroup (four workgroups per CU).
+// Records (k_pass_hull, k_filter_hull) leave room for the sample polygon,
+// its wedge table and the exact-test queue within 40 KiB per workgroup.
 template <>
 struct StageCap<Rec> {
-  static constexpr int value = 448;
+  static constexpr int value = 320;
 };
 
 // Exact-test queue of the hull path: points that pass neither cheap test
@@ -689,24 +704,37 @@ __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
     return;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
+  // Each round a workgroup tests kR records per thread and reserves room for
+  // all its survivors with one atomic (a counter shared by the whole grid
+  // serialises, so reservations are kept few).
+  constexpr uint32_t kR = 8;
+  constexpr uint32_t kChunk = kBlock * kR;
+  __shared__ uint32_t s_base;
   const uint32_t m = *cand_count;
-  for (uint32_t base = (blockIdx.x * kWaves + w) * 64; base < m; base += gridDim.x * kBlock) {
-    const uint32_t i = base + lane;
-    Rec r{};
-    bool keep = false;
-    if (i < m) {
-      r = cand[i];
-      keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
-                             hdr->vidx).keep;
+  for (uint32_t s0 = blockIdx.x * kChunk; s0 < m; s0 += gridDim.x * kChunk) {
+    Rec r[kR];
+    uint32_t km = 0, cnt = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kR; ++j) {
+      const uint32_t i = s0 + j * kBlock + threadIdx.x;
+      if (i < m) {
+        r[j] = cand[i];
+        if (classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF), r[j].i,
+                            o, hdr->vidx).keep) {
+          km |= 1u << j;
+          ++cnt;
+        }
+      }
     }
-    const uint64_t b = __ballot(keep);
-    if (!b) continue;
-    uint32_t pos = 0;
-    if (lane == 0) pos = atomicAdd(count_out, popc64(b));
-    pos = __shfl(pos, 0);
-    if (keep) surv[pos + popc64(b & lt)] = r;
+    uint32_t total;
+    const uint32_t off = block_excl_scan(cnt, total);
+    if (threadIdx.x == 0 && total) s_base = atomicAdd(count_out, total);
+    __syncthreads();
+    uint32_t q = s_base + off;
+#pragma unroll
+    for (uint32_t j = 0; j < kR; ++j)
+      if (km & (1u << j)) surv[q++] = r[j];
+    __syncthreads();  // s_base is rewritten next round
   }
 }
 
@@ -850,21 +878,33 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
 // Hull path from kSampleMin points, with the sample polygon built first: one
 // read of the points does pass 1 -- the exact 8-way extremes, per-workgroup
 // partials and the domain flag, as k_reduce8 -- and in the same pass keeps the
-// points not strictly inside the sample polygon as candidate records (disc
-// test, then the exact fan test through the per-wave queue). The octagon test
-// then runs on the candidates alone (cand_filter): every point it would
-// keep is either a candidate or strictly inside a polygon of input points,
-// which no hull vertex is. Without a usable polygon this is pass 1 only, and
-// k_filter_hull makes the second read.
+// points not strictly inside the sample polygon as candidate records (inner
+// region test, then the exact wedge test through the per-wave queue). The
+// octagon test then runs on the candidates alone (cand_filter): every point
+// it would keep is either a candidate or strictly inside a polygon of input
+// points, which no hull vertex is. Without a usable polygon this is pass 1
+// only, and k_filter_hull makes the second read.
+//
+// With a polygon, the extremes are taken over the points outside its inner
+// region (disc or octagon, see in_inner) only: a point strictly inside the
+// convex hull of other input points is not extreme in any direction, so no
+// key it would give can win. Points inside the region are finite and inside
+// the grid square, so their domain check is
+// the grid test alone, done as the largest fractional part of the scaled
+// coordinates (zero exactly when every one is a grid value); points outside
+// get their keys and the full check of keys_add (NaN, infinities, range
+// through the keys) when the exact-test queue drains, a wave at a time.
 __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ xy, uint32_t n,
                                                       uint32_t head, double* __restrict__ partials,
                                                       uint32_t* __restrict__ part_bad,
                                                       const SamplePoly* __restrict__ poly,
+                                                      SampleDirs* __restrict__ sd,
                                                       Rec* __restrict__ cand,
-                                                      uint32_t* __restrict__ cand_count) {
+                                                      uint32_t narrow_blocks) {
   constexpr int kCapW = StageCap<Rec>::value;
   __shared__ Rec s_buf[kWaves][kCapW];
   __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
+  __shared__ uint32_t s_lut[kLutBins];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
   __shared__ uint32_t s_bad;
@@ -872,12 +912,70 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t pnv = min(poly->nv, (uint32_t)kPolyMax);
   const bool use_sp = pnv >= 3;
-  float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+  const uint32_t* __restrict__ lut = sd->lut;
+  uint32_t* __restrict__ cand_count = &sd->cand;
+  __shared__ uint32_t s_est[kWaves];
+  // Inner region in grid units (scaled coordinates t = 2^20 x are exact):
+  // the disc, or the octagon when its area is larger (one test per point).
+  float gcx = 0.f, gcy = 0.f, gr2 = 0.f, gos = 0.f, got = 0.f;
+  int32_t pcxi = 0, pcyi = 0;
+  bool use_oct = false;
+  uint32_t act = gridDim.x;
+  auto in_oct = [&](float dx, float dy) {
+    const float ax = __builtin_fabsf(dx), ay = __builtin_fabsf(dy);
+    return (ax < gos) & (ay < gos) & (ax + ay < got);
+  };
+  auto inner = [&](float tx, float ty) {
+    const float dx = tx - gcx, dy = ty - gcy;
+    return use_oct ? in_oct(dx, dy) : __builtin_fmaf(dx, dx, dy * dy) < gr2;
+  };
+  if (use_sp) {
+    pcxi = poly->cx;
+    pcyi = poly->cy;
+    gcx = (float)pcxi;
+    gcy = (float)pcyi;
+    gr2 = poly->r2 * 0x1p40f;
+    gos = poly->os * kGridF;
+    got = poly->ot * kGridF;
+    const float cut = __builtin_fmaxf(2.0f * gos - got, 0.0f);
+    use_oct = 4.0f * gos * gos - 2.0f * cut * cut > 3.14159265f * gr2;
+    // Share of points outside the inner region, estimated on kEstPer kBlock
+    // points spread over the input (the same ones in every workgroup, so all take
+    // the same decision). Few: stream with narrow_blocks workgroups (fewer
+    // concurrent streams read HBM faster); the rest only write empty
+    // partials. Many: the whole grid, whose waves hide the exact tests.
+    float ex[kEstPer], ey[kEstPer];
+#pragma unroll
+    for (uint32_t e = 0; e < kEstPer; ++e) {
+      const size_t q = (size_t)((uint64_t(threadIdx.x + e * kBlock) * n) / (kBlock * kEstPer));
+      ex[e] = xy[2 * q];
+      ey[e] = xy[2 * q + 1];
+    }
+    uint32_t nout = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kEstPer; ++e) {
+      const uint64_t ob = __builtin_amdgcn_ballot_w64(!inner(ex[e] * kGridF, ey[e] * kGridF));
+      nout += popc64(ob);
+    }
+    if (lane == 0) s_est[w] = nout;
+    __syncthreads();
+    uint32_t est = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) est += s_est[i];
+    if (est * kWideRatio <= kBlock * kEstPer) act = min(narrow_blocks, gridDim.x);
+  }
+  if (blockIdx.x >= act) {
+    if (threadIdx.x == 0) {
+      Keys e;
+      keys_init(e);
+      keys_to_array(e, partials + size_t(blockIdx.x) * 8);
+      part_bad[blockIdx.x] = 0;
+    }
+    return;
+  }
   if (use_sp) {
     for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = poly->vx[i]; s_pvy[i] = poly->vy[i]; }
-    pcx = (float)poly->cx * (1.0f / kGridF);
-    pcy = (float)poly->cy * (1.0f / kGridF);
-    pr2 = poly->r2;
+    for (uint32_t i = threadIdx.x; i < kLutBins; i += kBlock) s_lut[i] = lut[i];
   }
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
@@ -885,6 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
   Keys k;
   keys_init(k);
   bool bad = false;
+  float frac = 0.f;         // largest fractional part of a scaled coordinate (inner points)
   uint32_t cw = 0, qn = 0;  // staged candidates, queued points (wave-uniform)
   auto flush = [&]() {
     uint32_t base = 0;
@@ -895,12 +994,17 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
     cw = 0;
   };
   auto outside = [&](float x, float y) {
-    return !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+    return !poly_lut_inside(s_pvx, s_pvy, pnv, s_lut, pcxi, pcyi, (int32_t)(x * kGridF),
+                            (int32_t)(y * kGridF));
   };
+  // Queued points (all outside the inner region): their keys, then the exact test.
   auto drain = [&](uint32_t base, uint32_t cnt) {
     float x = 0.f, y = 0.f;
     uint32_t g = 0;
-    if (lane < (int)cnt) { x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; g = s_qg[w][base + lane]; }
+    if (lane < (int)cnt) {
+      x = s_qx[w][base + lane]; y = s_qy[w][base + lane]; g = s_qg[w][base + lane];
+      keys_add(k, x, y, bad);
+    }
     wave_sync();
     const bool keep = lane < (int)cnt && outside(x, y);
     const uint64_t b = __ballot(keep);
@@ -909,10 +1013,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
     if (keep) s_buf[w][cw + popc64(b & lt)] = make_payload<Rec>(g, x, y);
     cw += popc64(b);
   };
-  auto push = [&](bool q, float x, float y, uint32_t g) {
-    const uint64_t m = __ballot(q);
+  // Points outside the inner region (mask = the wave's ballot) join the queue.
+  auto push = [&](uint64_t m, float x, float y, uint32_t g) {
     if (!m) return;
-    if (q) {
+    if ((m >> lane) & 1ull) {
       const uint32_t pos = qn + popc64(m & lt);
       s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = g;
     }
@@ -927,14 +1031,18 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
   const uint32_t nfull = (n - head) >> 1;
   const uint32_t gw = blockIdx.x * kWaves + w;
-  const uint32_t nw = gridDim.x * kWaves;
-  const uint32_t per_batch = kU * 64;
+  const uint32_t nw = act * kWaves;
+  const uint32_t per_batch = kUF * 64;
   const uint32_t nbatch = (nfull + per_batch - 1) / per_batch;
-  if (gw < nbatch) {
-    float4 cur[kU], nxt[kU];
+  // One streaming loop per mode, uniform over the grid: no polygon (keys of
+  // every point), inner disc, inner octagon.
+  auto stream = [&](auto mode_tag) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    constexpr bool SP = MODE != 0;
+    float4 cur[kUF], nxt[kUF];
     uint32_t b = gw;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUF; ++u) {
       const uint32_t q = b * per_batch + u * 64 + lane;
       cur[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
     }
@@ -944,45 +1052,68 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
       const bool more = bn < nbatch;
       if (more) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < kUF; ++u) {
           const uint32_t q = bn * per_batch + u * 64 + lane;
           nxt[u] = ld_stream(&p4[q < nfull ? q : nfull - 1]);
         }
       }
+      if constexpr (!SP) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        // Lanes past the end hold a copy of the last pair: harmless for the
-        // extremes, excluded from the candidates.
-        keys_add(k, cur[u].x, cur[u].y, bad);
-        keys_add(k, cur[u].z, cur[u].w, bad);
-      }
-      if (use_sp) {
-        // Disc tests of the whole batch first, then one branch per batch:
-        // a branch on each row's vote stalls the wave on every row.
-        uint32_t tm = 0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const uint32_t q = b * per_batch + u * 64 + lane;
-          const bool val = q < nfull;
-          const float4 v = cur[u];
-          tm |= (val & !in_disc(v.x, v.y, pcx, pcy, pr2)) ? 1u << (2 * u) : 0u;
-          tm |= (val & !in_disc(v.z, v.w, pcx, pcy, pr2)) ? 2u << (2 * u) : 0u;
+        for (int u = 0; u < kUF; ++u) {
+          // Lanes past the end hold a copy of the last pair: harmless for
+          // the extremes.
+          keys_add(k, cur[u].x, cur[u].y, bad);
+          keys_add(k, cur[u].z, cur[u].w, bad);
         }
-        if (__ballot(tm != 0)) {
+      } else {
+        // Grid check and inner-region votes for the whole batch, then one branch:
+        // a branch on each row's vote stalls the wave on every row. Lanes
+        // past the end hold a copy of the last pair and vote no.
+        uint64_t mk[2 * kUF];
+        uint64_t any = 0;
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < kUF; ++u) {
+          const float4 v = cur[u];
+          const float t0 = v.x * kGridF, t1 = v.y * kGridF, t2 = v.z * kGridF, t3 = v.w * kGridF;
+          frac = __builtin_fmaxf(frac, __builtin_fmaxf(__builtin_amdgcn_fractf(t0),
+                                                       __builtin_amdgcn_fractf(t1)));
+          frac = __builtin_fmaxf(frac, __builtin_fmaxf(__builtin_amdgcn_fractf(t2),
+                                                       __builtin_amdgcn_fractf(t3)));
+          bool i0, i1;
+          if constexpr (MODE == 1) {
+            const float dx0 = t0 - gcx, dy0 = t1 - gcy, dx1 = t2 - gcx, dy1 = t3 - gcy;
+            i0 = __builtin_fmaf(dx0, dx0, dy0 * dy0) < gr2;
+            i1 = __builtin_fmaf(dx1, dx1, dy1 * dy1) < gr2;
+          } else {
+            i0 = in_oct(t0 - gcx, t1 - gcy);
+            i1 = in_oct(t2 - gcx, t3 - gcy);
+          }
+          const uint64_t val = __builtin_amdgcn_ballot_w64(b * per_batch + u * 64 + lane < nfull);
+          mk[2 * u] = __builtin_amdgcn_ballot_w64(!i0) & val;
+          mk[2 * u + 1] = __builtin_amdgcn_ballot_w64(!i1) & val;
+          any |= mk[2 * u] | mk[2 * u + 1];
+        }
+        if (any) {
+#pragma unroll
+          for (int u = 0; u < kUF; ++u) {
             const uint32_t g = head + 2 * (b * per_batch + u * 64 + lane);
-            push((tm >> (2 * u)) & 1u, cur[u].x, cur[u].y, g);
-            push((tm >> (2 * u)) & 2u, cur[u].z, cur[u].w, g + 1);
+            push(mk[2 * u], cur[u].x, cur[u].y, g);
+            push(mk[2 * u + 1], cur[u].z, cur[u].w, g + 1);
           }
         }
       }
       if (!more) break;
 #pragma unroll
-      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+      for (int u = 0; u < kUF; ++u) cur[u] = nxt[u];
       b = bn;
     }
+  };
+  if (gw < nbatch) {
+    if (!use_sp) stream(IntC<0>{});
+    else if (!use_oct) stream(IntC<1>{});
+    else stream(IntC<2>{});
   }
+  bad |= frac != 0.f;
   if (use_sp) {
     if (qn) drain(0, qn);
     if (cw) flush();
@@ -1189,13 +1320,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
     const SamplePoly* __restrict__ sp = &polys[st.set];
     const uint32_t pnv = min(sp->nv, (uint32_t)kPolyMax);
     const bool use_sp = pnv >= 3;
-    float pcx = 0.f, pcy = 0.f, pr2 = 0.f;
+    float pcx = 0.f, pcy = 0.f, pr2 = 0.f, pos = 0.f, pot = 0.f;
     __syncthreads();  // the previous tile is done with s_pvx / s_pvy
     if (use_sp) {
       for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = sp->vx[i]; s_pvy[i] = sp->vy[i]; }
       pcx = (float)sp->cx * (1.0f / kGridF);
       pcy = (float)sp->cy * (1.0f / kGridF);
       pr2 = sp->r2;
+      pos = sp->os;
+      pot = sp->ot;
     }
     __syncthreads();
     const uint32_t base = (uint32_t)off[st.set];
@@ -1251,8 +1384,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
       if (__ballot(need0 | need1)) {
         bool t0 = need0, t1 = need1;
         if (use_sp) {
-          t0 = t0 & !in_disc(v.x, v.y, pcx, pcy, pr2);
-          t1 = t1 & !in_disc(v.z, v.w, pcx, pcy, pr2);
+          t0 = t0 & !in_inner(v.x, v.y, pcx, pcy, pr2, pos, pot);
+          t1 = t1 & !in_inner(v.z, v.w, pcx, pcy, pr2, pos, pot);
         }
         push(t0, v.x, v.y, g - base);
         push(t1, v.z, v.w, g + 1 - base);
@@ -1323,9 +1456,9 @@ hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, ui
 
 hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
                             uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
-                            uint32_t blocks, hipStream_t st) {
+                            uint32_t blocks, uint32_t narrow_blocks, hipStream_t st) {
   hipLaunchKernelGGL(k_pass_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad,
-                     poly, cand, &static_cast<SampleDirs*>(scratch)->cand);
+                     poly, static_cast<SampleDirs*>(scratch), cand, narrow_blocks);
   return hipGetLastError();
 }
 

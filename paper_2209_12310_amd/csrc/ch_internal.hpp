@@ -82,6 +82,7 @@ struct Rec {           // a candidate hull point: grid coordinates + index
 // a hull vertex. Tested after the octagon's box through a disc around an
 // inner grid point, then exactly.
 constexpr int kPolyMax = 512;              // directions (and at most vertices), single set
+constexpr uint32_t kLutBins = 2048;        // single set: pseudo-angle bins of the wedge table
 constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
 constexpr uint32_t kSampleBlocks = kSampleN / kSamplePer;
@@ -95,6 +96,8 @@ struct SamplePoly {
   int32_t cx, cy;      // grid point strictly inside the polygon
   float r2;            // squared radius (float units) of a disc about (cx, cy) inside
                        // the polygon, rounded down with a margin for fp32 tests
+  float os, ot;        // octagon |dx| <= os, |dy| <= os, |dx| + |dy| <= ot (float
+                       // units) about (cx, cy) inside the polygon; 0 when none
   int32_t vx[kPolyMax], vy[kPolyMax];  // counter-clockwise, strictly convex
 };
 
@@ -145,7 +148,8 @@ inline Layout layout(uint32_t n) {
   L.wcnt = o;      o = align_up(o + 2 * (chain_cap / kHullTile + 4) * 4, 256);
   // Refined filter: the sample polygon and the direction maxima.
   L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
-  L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kSampleBlocks) * kPolyMax * 16, 256);
+  L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kLutBins) * 4 +
+                                       size_t(kSampleBlocks) * kPolyMax * 16, 256);
   L.total = o;
   return L;
 }

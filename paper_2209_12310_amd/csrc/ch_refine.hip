@@ -68,7 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
   }
 }
 
-static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256 + size_t(kSampleBlocks) * kPolyMax * 16,
+static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256 + size_t(kLutBins) * 4 +
+                                         size_t(kSampleBlocks) * kPolyMax * 16,
               "workspace slot of the direction maxima");
 
 __global__ __launch_bounds__(kBlock) void k_sample_dirs(const float* __restrict__ xy, uint32_t n,
@@ -107,7 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_sample_reduce(const float* __restric
 #pragma unroll 8
   for (uint32_t b = ln; b < kSampleBlocks; b += kLanes) {
     const int4 v = sd->part[b][d];
-    best = v.x > best.x ? v : best;
+    const bool gt = v.x > best.x;  // per component: a select of the whole int4 goes through memory
+    best.x = gt ? v.x : best.x;
+    best.y = gt ? v.y : best.y;
+    best.z = gt ? v.z : best.z;
   }
 #pragma unroll
   for (uint32_t o = 1; o < kLanes; o <<= 1) {
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_reduce(const float* __restric
     py[e] = __hip_atomic_load(&sd->vy[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  build_poly(px, py, kPolyMax, poly);
+  build_poly(px, py, kPolyMax, poly, sd->lut);
 }
 
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,

@@ -50,16 +50,144 @@ __device__ __forceinline__ int64_t orient64(int64_t ax, int64_t ay, int64_t bx, 
   return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
 }
 
+// Pseudo-angle of the direction (dx, dy) != 0: a strictly increasing function
+// of its angle from the +x axis counter-clockwise, onto [0, 4) -- the sine of
+// the L1-normalised vector, unrolled per quadrant (0, 1, 2, 3 at the +x, +y,
+// -x, -y axes). pangle64 is exact up to one rounding of the division;
+// pangle32 (for the query points) is within 4e-7 of the exact value for
+// integer inputs below 2^21 in magnitude.
+__device__ __forceinline__ double pangle64(double dx, double dy) {
+  const double a = dy / (__builtin_fabs(dx) + __builtin_fabs(dy));
+  return dx >= 0.0 ? (dy >= 0.0 ? a : 4.0 + a) : 2.0 - a;
+}
+__device__ __forceinline__ float pangle32(float dx, float dy) {
+  const float a = dy * __builtin_amdgcn_rcpf(__builtin_fabsf(dx) + __builtin_fabsf(dy));
+  return dx >= 0.f ? (dy >= 0.f ? a : 4.f + a) : 2.f - a;
+}
+
+// Wedge table of a polygon about its centre c: the vertices, in
+// counter-clockwise order starting at the smallest pseudo-angle, split the
+// plane around c into wedges (wedge j between vertices j and j+1, the last
+// one wrapping through angle 0). Bin k of kLutBins covers the pseudo-angles
+// [k w - eps, (k+1) w + eps], w = 4 / kLutBins, eps = 2^-16 (far above the
+// error of pangle32); its entry holds the first wedge meeting that interval
+// (low 16 bits) and the number of consecutive wedges that do (high 16 bits).
+constexpr double kLutEps = 0x1p-16;
+
+// Exact: p strictly inside the polygon. A point is strictly inside exactly
+// when it is strictly left of every side, and one that is not is on or right
+// of the side of the wedge its direction from c falls in; the bin of its
+// computed pseudo-angle lists that wedge (the error is below eps), so testing
+// the listed sides decides. c itself is strictly inside.
+__device__ __forceinline__ bool poly_lut_inside(const int32_t* vx, const int32_t* vy, uint32_t nv,
+                                                const uint32_t* lut, int32_t cx, int32_t cy,
+                                                int32_t px, int32_t py) {
+  const float dx = (float)(px - cx), dy = (float)(py - cy);
+  if (dx == 0.f && dy == 0.f) return true;
+  const float th = pangle32(dx, dy);
+  const uint32_t k = min((uint32_t)(th * (float)(kLutBins / 4)), kLutBins - 1);
+  const uint32_t e = lut[k];
+  uint32_t j = e & 0xffffu;
+  bool in = true;
+  for (uint32_t c = e >> 16; c > 0; --c) {
+    const uint32_t jn = j + 1 < nv ? j + 1 : 0;
+    in = in && cross3(vx[j], vy[j], vx[jn], vy[jn], px, py) > 0.0;
+    j = jn;
+  }
+  return in;
+}
+
+// Whole workgroup: the inner octagon |dx| <= s, |dy| <= s, |dx| + |dy| <= t
+// (s <= t <= 2s) about c of the polygon px/py[0..m) (m = 0: none), written
+// as out->os, out->ot in float units. A side with o = twice the area of its
+// triangle with c and M, m' = the larger and smaller of |ex|, |ey| holds the
+// octagon when s (M - m') + t m' <= o (the octagon's farthest vertex from the
+// side's line, scaled by |e|). s_max = min o / M; for eight candidate s
+// (s_max (1 - 2^-k), k = 3..10) the largest t follows, and the largest area
+// 4 s^2 - 2 (2 s - t)^2 wins. The
+// float values are checked against every side in exact arithmetic (products
+// of a float and an integer below 2^21 are exact in fp64); a failure drops
+// the octagon. mx/my: LDS scratch of kPolyMax int32 each.
+__device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_t m, int32_t cx,
+                                   int32_t cy, int32_t* mx, int32_t* my, SamplePoly* __restrict__ out) {
+  constexpr int kCand = 8;
+  __shared__ double s_o[kPolyMax];
+  __shared__ double s_red[kWaves][kCand];
+  __shared__ double s_smax[kWaves];
+  __shared__ uint32_t s_fail;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double smax = __builtin_inf();
+  for (uint32_t j = threadIdx.x; j < m; j += kBlock) {
+    const uint32_t k = j + 1 < m ? j + 1 : 0;
+    const int64_t ex = (int64_t)px[k] - px[j], ey = (int64_t)py[k] - py[j];
+    const int64_t ax = ex < 0 ? -ex : ex, ay = ey < 0 ? -ey : ey;
+    s_o[j] = (double)orient64(px[j], py[j], px[k], py[k], cx, cy);
+    mx[j] = (int32_t)(ax > ay ? ax : ay);
+    my[j] = (int32_t)(ax > ay ? ay : ax);
+    smax = __builtin_fmin(smax, s_o[j] / (double)mx[j]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmin(smax, __shfl_xor(smax, o));
+  if (lane == 0) s_smax[w] = smax;
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+  smax = s_smax[0];
+#pragma unroll
+  for (int i = 1; i < kWaves; ++i) smax = __builtin_fmin(smax, s_smax[i]);
+  // Thread: candidate c = tid % 8 (s = smax (1 - 2^-(c+3))), sides tid / 8,
+  // + 32, ... (near-axis sides bound t hard when s is close to smax).
+  const uint32_t c = threadIdx.x % kCand, sl = threadIdx.x / kCand;
+  const double sc = smax * (1.0 - __builtin_ldexp(1.0, -(int)c - 3));
+  double t = 2.0 * sc;
+  for (uint32_t j = sl; j < m; j += kBlock / kCand)
+    if (my[j] > 0) t = __builtin_fmin(t, (s_o[j] - sc * (double)(mx[j] - my[j])) / (double)my[j]);
+#pragma unroll
+  for (int o = 32; o >= kCand; o >>= 1) t = __builtin_fmin(t, __shfl_xor(t, o));
+  if (lane < kCand) s_red[w][lane] = t;
+  __syncthreads();
+  __shared__ float s_os, s_ot;
+  if (threadIdx.x == 0) {
+    double best = -1.0, bs = 0.0, bt = 0.0;
+    for (int i = 0; i < kCand && m >= 3; ++i) {
+      double ti = s_red[0][i];
+      for (int q = 1; q < kWaves; ++q) ti = __builtin_fmin(ti, s_red[q][i]);
+      const double si = smax * (1.0 - __builtin_ldexp(1.0, -i - 3));
+      const double a = 4.0 * si * si - 2.0 * (2.0 * si - ti) * (2.0 * si - ti);
+      if (si > 0.0 && ti >= si && a > best) { best = a; bs = si; bt = ti; }
+    }
+    // grid units -> float units, shrunk by a relative 2^-20
+    s_os = best > 0.0 ? (float)(bs * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
+    s_ot = best > 0.0 ? (float)(bt * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
+  }
+  __syncthreads();
+  const double gs = (double)s_os * 0x1p20, gt = (double)s_ot * 0x1p20;  // exact
+  for (uint32_t j = threadIdx.x; j < m; j += kBlock)
+    if (!(gs * (double)(mx[j] - my[j]) + gt * (double)my[j] <= s_o[j])) s_fail = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const bool keep = m >= 3 && s_fail == 0 && s_os > 0.0f;
+    out->os = keep ? s_os : 0.0f;
+    out->ot = keep ? s_ot : 0.0f;
+  }
+  __syncthreads();
+}
+
 // Whole workgroup. px/py[0..m0) (LDS) hold the extreme points in direction
-// order; writes the SamplePoly. Steps: drop repeats of the previous point
-// (cyclically), drop points where the boundary does not turn left, then
-// verify and measure in wave 0: every turn strictly left, the rounded vertex
-// mean c strictly left of every side, exactly one side crossing the line
-// y = c.y upwards (one turn around c), and r2 = the squared distance from c
-// to the nearest side line, rounded down with a relative margin of 2^-19.
-__device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SamplePoly* __restrict__ out) {
+// order; writes the SamplePoly, and with lut != null its wedge table. Steps:
+// drop repeats of the previous point (cyclically), drop points where the
+// boundary does not turn left, then verify and measure in wave 0: every turn
+// strictly left, the centre c strictly left of every side, exactly one side
+// crossing the line y = c.y upwards (one turn around c); r2 = the squared
+// distance from c to the nearest side line, rounded down with a relative
+// margin of 2^-19; then the inner octagon (see fit_octagon). With a table
+// the vertices are stored from the one of
+// smallest pseudo-angle about c on; a sequence of pseudo-angles that does not
+// wrap exactly once disables the polygon.
+__device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SamplePoly* __restrict__ out,
+                                  uint32_t* __restrict__ lut = nullptr) {
   __shared__ int32_t qx[kPolyMax], qy[kPolyMax];
-  __shared__ uint32_t s_ok;
+  __shared__ uint32_t s_ok, s_m, s_desc, s_rot;
+  __shared__ int32_t s_cx, s_cy;
   const uint32_t E = (m0 + kBlock - 1) / kBlock;
   const uint32_t j0 = threadIdx.x * E;
   // 1. repeats
@@ -147,7 +275,11 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
     }
     if (lane == 0) {
       s_ok = good ? 1u : 0u;
-      out->nv = good ? m : 0u;
+      s_m = m;
+      s_cx = (int32_t)cx;
+      s_cy = (int32_t)cy;
+      s_desc = 0;
+      s_rot = 0;
       out->cx = (int32_t)cx;
       out->cy = (int32_t)cy;
       // grid units^2 -> float units^2 (2^-40), then the margin.
@@ -155,8 +287,85 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
     }
   }
   __syncthreads();
-  if (s_ok)
-    for (uint32_t j = threadIdx.x; j < m; j += kBlock) { out->vx[j] = px[j]; out->vy[j] = py[j]; }
+  const bool ok = s_ok != 0;
+  fit_octagon(px, py, ok ? m : 0u, s_cx, s_cy, qx, qy, out);
+  if (!lut) {
+    if (ok)
+      for (uint32_t j = threadIdx.x; j < m; j += kBlock) { out->vx[j] = px[j]; out->vy[j] = py[j]; }
+    if (threadIdx.x == 0) out->nv = ok ? m : 0u;
+    return;
+  }
+  // 4. wedge table: rotate to the smallest pseudo-angle, then bin.
+  __shared__ double s_t[kPolyMax];
+  const double ccx = s_cx, ccy = s_cy;
+  if (ok) {
+    for (uint32_t j = threadIdx.x; j < m; j += kBlock)
+      s_t[j] = pangle64((double)px[j] - ccx, (double)py[j] - ccy);
+  }
+  __syncthreads();
+  if (ok) {
+    for (uint32_t j = threadIdx.x; j < m; j += kBlock) {
+      const uint32_t p = j ? j - 1 : m - 1;
+      if (!(s_t[j] > s_t[p])) { atomicAdd(&s_desc, 1u); s_rot = j; }
+    }
+  }
+  __syncthreads();
+  const bool use = ok && s_desc == 1;
+  if (use) {
+    const uint32_t r = s_rot;
+    for (uint32_t j = threadIdx.x; j < m; j += kBlock) {
+      const uint32_t q = j + r < m ? j + r : j + r - m;
+      qx[j] = px[q];
+      qy[j] = py[q];
+    }
+  }
+  __syncthreads();
+  if (use) {
+    for (uint32_t j = threadIdx.x; j < m; j += kBlock) {
+      s_t[j] = pangle64((double)qx[j] - ccx, (double)qy[j] - ccy);
+      out->vx[j] = qx[j];
+      out->vy[j] = qy[j];
+    }
+  }
+  __syncthreads();
+  // Bin k's interval ends, looked up by a binary search over the sorted
+  // vertex angles: the wedge holding an angle th is the last vertex j with
+  // t_j <= th, or the wrapping wedge m-1 when th < t_0. Each thread takes
+  // kLutBins / kBlock consecutive bins and runs their searches in lockstep
+  // (independent LDS reads in flight together).
+  constexpr uint32_t kQ = kLutBins / kBlock;
+  static_assert(kLutBins % kBlock == 0, "whole bins per thread");
+  constexpr double w = 4.0 / (double)kLutBins;
+  if (use) {
+    double th[2 * kQ];
+    uint32_t pos[2 * kQ];
+#pragma unroll
+    for (uint32_t i = 0; i < kQ; ++i) {
+      const uint32_t k = threadIdx.x * kQ + i;
+      double lo = (double)k * w - kLutEps, hi = (double)(k + 1) * w + kLutEps;
+      th[2 * i] = lo < 0.0 ? lo + 4.0 : lo;
+      th[2 * i + 1] = hi >= 4.0 ? hi - 4.0 : hi;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 2 * kQ; ++q) pos[q] = 0;
+    uint32_t step = 1;
+    while (step * 2 <= m) step *= 2;
+    for (; step > 0; step >>= 1) {
+#pragma unroll
+      for (uint32_t q = 0; q < 2 * kQ; ++q) {
+        const uint32_t c = pos[q] + step;
+        if (c < m && s_t[c] <= th[q]) pos[q] = c;
+      }
+    }
+    const double t0 = s_t[0];
+#pragma unroll
+    for (uint32_t i = 0; i < kQ; ++i) {
+      const uint32_t a = th[2 * i] < t0 ? m - 1 : pos[2 * i];
+      const uint32_t b = th[2 * i + 1] < t0 ? m - 1 : pos[2 * i + 1];
+      lut[threadIdx.x * kQ + i] = a | (((b >= a ? b - a : b + m - a) + 1) << 16);
+    }
+  }
+  if (threadIdx.x == 0) out->nv = use ? m : 0u;
 }
 
 // Largest and smallest dot product over the sample points sp[0..cnt) (LDS)
@@ -191,9 +400,11 @@ struct SampleDirs {
   uint32_t arrive;
   uint32_t cand;       // candidate records written by the fused pass
   uint32_t pad[62];
+  uint32_t lut[kLutBins];              // wedge table of the polygon (see build_poly)
   int4 part[kSampleBlocks][kPolyMax];  // (dot product, x, y, 0)
 };
 constexpr uint32_t kReduceDirsPerBlock = 8;
+
 constexpr uint32_t kSampleReduceBlocks = kPolyMax / kReduceDirsPerBlock;
 
 }  // namespace chk

@@ -83,6 +83,7 @@ SINGLE = {
     "uniform_1e6": ("uniform", 1_000_000, 0),
     "normal_1e8": ("normal", 100_000_000, 1),
     "annulus_1e8": ("annulus", 100_000_000, 2),
+    "uniform_1e8": ("uniform", 100_000_000, 5),
 }
 
 

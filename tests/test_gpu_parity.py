@@ -221,7 +221,7 @@ def test_uniform_1e6_full(ctx):
     _check_hull(ctx, xy)
 
 
-@pytest.mark.parametrize("name", ["normal_1e8", "annulus_1e8"])
+@pytest.mark.parametrize("name", ["normal_1e8", "annulus_1e8", "uniform_1e8"])
 def test_full_size(ctx, name):
     """Full 10^8-point configurations: complete survivor list and hull."""
     _say(f"full {name}: generating")

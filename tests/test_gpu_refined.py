@@ -70,7 +70,15 @@ def _cases(scale_min, m=60):
     line = np.stack([7 * k, 3 * k + 11], 1)
     circle = np.asarray(lattice_circle(5 * 13 * 17 * 29), np.int64)
     circ_inner = rng.integers(-22000, 22000, (n, 2)) + (1 << 19)
+    # points on rays from the centre (through the polygon's vertices and
+    # their wedge boundaries), to the ray ends, which are the hull
+    dirs = np.array([(1, 0), (3, 1), (2, 1), (1, 1), (1, 2), (1, 3), (0, 1), (-1, 3), (-1, 1),
+                     (-3, 1), (-1, 0), (-2, -1), (-1, -1), (-1, -2), (0, -1), (1, -1), (3, -2)])
+    reps = n // len(dirs) + 1
+    t = np.arange(1, reps + 1) * (60000 // reps + 1) // 8
+    rays = ((1 << 19) + dirs[:, None, :] * t[None, :, None]).reshape(-1, 2)[:n]
     return {
+        "rays": _grid(rays[rng.permutation(len(rays))]),
         # every point twice; the copy at the smaller index is the one reported
         "reversed_duplicates": np.concatenate([ann[::-1], ann]),
         "square_sides": _square_boundary_with_interior(n, 4096, 83),
@@ -116,6 +124,27 @@ def test_domain_error_at_sampled_points(ctx, where):
     xy[i, 1] = np.float32(np.nan)
     with pytest.raises(ch.DomainError):
         ctx.hull(_dev(xy))
+
+
+@pytest.mark.parametrize("where", [1, 4097, "middle", "second_last", "last"])
+def test_domain_error_inside_polygon(ctx, where):
+    """Off-grid values deep inside the data (inside the sample polygon's
+    disc, where the single-read pass skips the extreme keys) still give the
+    call's domain error: half a grid step and a sixteenth of one."""
+    import paper_2209_12310_amd as ch
+    n = SAMPLE_MIN + 999
+    base = workloads.normal(n, 95)
+    i = {"middle": n // 2, "second_last": n - 2, "last": n - 1}.get(where, where)
+    for off in (2.0 ** -21, 2.0 ** -24):
+        _say(f"refined domain error inside the polygon at {where}, offset {off}")
+        xy = base.copy()
+        xy[i] = (np.float32(0.5 + off), np.float32(0.5))
+        with pytest.raises(ch.DomainError):
+            ctx.hull(_dev(xy))
+    # the same inputs on the grid are accepted
+    xy = base.copy()
+    xy[i] = (np.float32(0.5), np.float32(0.5))
+    assert np.array_equal(ctx.hull(_dev(xy)), oracle.hull(xy))
 
 
 def test_batch_refined(ctx):
