@@ -50,7 +50,9 @@ def stage_bytes(n: int, info: dict) -> dict:
     b["per_point"] = round(b["total"] / n, 3)
     return b
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_normal_1e8.json")
-KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp"]
+KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp",
+                  "paper_2209_12310_amd/csrc/ch_device.hpp", "paper_2209_12310_amd/csrc/ch_refine.hpp",
+                  "paper_2209_12310_amd/csrc/ch_refine.hip"]
 
 
 def log(msg: str) -> None:
@@ -434,7 +436,7 @@ def main() -> int:
                                      "octagon_survivors": survivors, "hull_info": info,
                                      "h": int(hull.size)}}
     if not args.no_extra:
-        for name in ("uniform_1e6", "annulus_1e8"):
+        for name in ("uniform_1e8", "annulus_1e8", "uniform_1e6"):
             out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 2)
             torch.cuda.synchronize()
     if not args.no_batch:
