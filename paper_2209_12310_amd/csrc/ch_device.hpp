@@ -52,6 +52,8 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
 
 // Orders this wave's LDS accesses before and after the call (the waves of a
 // workgroup are not synchronised).
+__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -457,7 +457,6 @@ __device__ __forceinline__ Verdict classify(float x, float y, uint32_t gidx,
   return v;
 }
 
-__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
 // Pass 2 of ch_filter (the survivor list in ascending index order; the hull
 // path uses k_filter_hull below): persistent grid of G2 workgroups. Workgroup ids come from

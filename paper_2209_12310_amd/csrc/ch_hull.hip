@@ -281,6 +281,193 @@ struct WinSmem {
 template <int T>
 constexpr int maxc() { return (T / kBlock + 1) / 2; }
 
+// ------------------------------------------------ small inputs: one wave per chain
+//
+// When the pre-filter leaves few candidates (at most kSmallChain per chain),
+// each chain is built by one wave with no workgroup barrier inside: a
+// register bitonic sort, duplicate removal, and a parallel vertex test. For
+// points p_0 < ... < p_(m-1) in (x, y) order, p_i is a strict lower-chain
+// vertex exactly when orient(p_j, p_i, p_k) > 0 for every j < i < k, i.e.
+// for the j whose direction p_j -> p_i turns furthest counter-clockwise and
+// the k whose direction p_i -> p_k turns furthest clockwise (both sets of
+// directions lie within a half-turn, so these are well defined); the upper
+// chain mirrors the signs. Each lane finds the two extreme neighbours of its
+// points in one pass over the chain, then tests those triples. Item e of
+// lane l is element 64 e + l.
+constexpr uint32_t kSmallChain = 128;
+
+// Ascending sort of 128 64-bit keys, two per lane.
+__device__ __forceinline__ void wave_sort128(uint64_t& v0, uint64_t& v1, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j == 64) {  // k == 128: the pair of one lane, ascending
+        const uint64_t lo = v0 < v1 ? v0 : v1, hi = v0 < v1 ? v1 : v0;
+        v0 = lo;
+        v1 = hi;
+      } else {
+        const uint64_t o0 = __shfl_xor(v0, j), o1 = __shfl_xor(v1, j);
+        const bool low = (lane & j) == 0;
+        const bool asc0 = (lane & k) == 0, asc1 = ((lane + 64) & k) == 0;
+        v0 = (asc0 == low) ? (o0 < v0 ? o0 : v0) : (o0 > v0 ? o0 : v0);
+        v1 = (asc1 == low) ? (o1 < v1 ? o1 : v1) : (o1 > v1 ? o1 : v1);
+      }
+    }
+  }
+}
+
+// Whole workgroup. The `kept` (1..2 kSmallChain) candidates are in sm.a.key
+// (x<<44 | y<<24 | position) with their indices in sm.b.pidx. Wave 0 builds
+// the lower chain into px/py/pi, wave 1 the upper chain into a.u / b.ui
+// (both from the lexicographic minimum to the maximum, ends included).
+// Returns false, with sm untouched, when a chain has more than kSmallChain
+// candidates.
+template <int T>
+__device__ bool small_chains(HullSmem<T>& sm, uint32_t kept, uint32_t& nl, uint32_t& nu) {
+  __shared__ uint32_t s_n[2];
+  __shared__ uint64_t s_key[2][kSmallChain];
+  __shared__ uint32_t s_id[2][kSmallChain];
+  __shared__ int32_t s_x[2][kSmallChain], s_y[2][kSmallChain];
+  __shared__ uint32_t s_ui[2][kSmallChain];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint64_t sel[4] = {0, 0, 0, 0};
+  uint64_t kin[4];
+  if (w < 2) {
+    bool v[4];
+    uint64_t mn = ~0ull, mx = 0ull;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = (uint32_t)(lane + 64 * e) < kept;
+      kin[e] = v[e] ? sm.a.key[lane + 64 * e] : ~0ull;
+      mn = kin[e] < mn ? kin[e] : mn;
+      mx = v[e] && kin[e] > mx ? kin[e] : mx;
+    }
+    // lexicographic minimum and maximum (keys order by x, then y)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    const int32_t ax = (int32_t)(mn >> 44), ay = (int32_t)((mn >> 24) & 0xFFFFFu);
+    const int32_t bx = (int32_t)(mx >> 44), by = (int32_t)((mx >> 24) & 0xFFFFFu);
+    uint32_t c = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bool in = false;
+      if (v[e]) {
+        const int32_t x = (int32_t)(kin[e] >> 44), y = (int32_t)((kin[e] >> 24) & 0xFFFFFu);
+        const double cr = cross3(ax, ay, bx, by, x, y);
+        in = (x == ax && y == ay) || (x == bx && y == by) || (w == 0 ? cr < 0.0 : cr > 0.0);
+      }
+      sel[e] = __builtin_amdgcn_ballot_w64(in);
+      c += popc64(sel[e]);
+    }
+    if (lane == 0) s_n[w] = c;
+  }
+  __syncthreads();
+  if (s_n[0] > kSmallChain || s_n[1] > kSmallChain) return false;
+  int32_t ox[2] = {0, 0}, oy[2] = {0, 0};
+  uint32_t oi[2] = {0, 0};
+  bool vert[2] = {false, false};
+  if (w < 2) {
+    // compact the chain's candidates, sort them, drop repeats (each
+    // distinct point keeps its smallest index)
+    const uint32_t c = s_n[w];
+    uint32_t base = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if ((sel[e] >> lane) & 1ull) s_key[w][base + popc64(sel[e] & lt)] = kin[e];
+      base += popc64(sel[e]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint64_t v0 = (uint32_t)lane < c ? s_key[w][lane] : ~0ull;
+    uint64_t v1 = (uint32_t)lane + 64 < c ? s_key[w][lane + 64] : ~0ull;
+    wave_sort128(v0, v1, lane);
+    __builtin_amdgcn_wave_barrier();
+    s_key[w][lane] = v0;
+    s_key[w][lane + 64] = v1;
+    s_id[w][lane] = (uint32_t)lane < c ? sm.b.pidx[v0 & 0xFFFFFFu] : 0u;
+    s_id[w][lane + 64] = (uint32_t)lane + 64 < c ? sm.b.pidx[v1 & 0xFFFFFFu] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t fm[2];
+    uint64_t upt[2];
+    uint32_t umi[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const uint32_t i = (uint32_t)lane + 64 * e;
+      const uint64_t pt = s_key[w][i] >> 24;
+      const bool first = i < c && (i == 0 || (s_key[w][i - 1] >> 24) != pt);
+      uint32_t mi = s_id[w][i];
+      if (first)
+        for (uint32_t q = i + 1; q < c && (s_key[w][q] >> 24) == pt; ++q) mi = s_id[w][q] < mi ? s_id[w][q] : mi;
+      fm[e] = __builtin_amdgcn_ballot_w64(first);
+      upt[e] = pt;
+      umi[e] = mi;
+    }
+    const uint32_t m = popc64(fm[0]) + popc64(fm[1]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if ((fm[e] >> lane) & 1ull) {
+        const uint32_t pos = (e ? popc64(fm[0]) : 0u) + popc64(fm[e] & lt);
+        s_x[w][pos] = (int32_t)(upt[e] >> 20);
+        s_y[w][pos] = (int32_t)(upt[e] & 0xFFFFFu);
+        s_ui[w][pos] = umi[e];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // sg = +1 for the lower chain, -1 for the upper one (mirrored signs)
+    const double sg = w == 0 ? 1.0 : -1.0;
+    const uint32_t i0 = (uint32_t)lane, i1 = (uint32_t)lane + 64;
+    const int32_t x0 = i0 < m ? s_x[w][i0] : 0, y0 = i0 < m ? s_y[w][i0] : 0;
+    const int32_t x1 = i1 < m ? s_x[w][i1] : 0, y1 = i1 < m ? s_y[w][i1] : 0;
+    int32_t jx0 = 0, jy0 = 0, kx0 = 0, ky0 = 0, jx1 = 0, jy1 = 0, kx1 = 0, ky1 = 0;
+    bool hj0 = false, hk0 = false, hj1 = false, hk1 = false;
+#pragma unroll 4
+    for (uint32_t q = 0; q < m; ++q) {
+      const int32_t qx = s_x[w][q], qy = s_y[w][q];  // one address: an LDS broadcast
+      // left of i: keep the direction q -> i furthest counter-clockwise
+      // (lower) / clockwise (upper); right of i: the direction i -> q
+      // furthest clockwise (lower) / counter-clockwise (upper)
+      {
+        const double o = sg * cross3(x0, y0, q < i0 ? jx0 : kx0, q < i0 ? jy0 : ky0, qx, qy);
+        if (q < i0 && (!hj0 || o > 0.0)) { jx0 = qx; jy0 = qy; hj0 = true; }
+        if (q > i0 && (!hk0 || o < 0.0)) { kx0 = qx; ky0 = qy; hk0 = true; }
+      }
+      {
+        const double o = sg * cross3(x1, y1, q < i1 ? jx1 : kx1, q < i1 ? jy1 : ky1, qx, qy);
+        if (q < i1 && (!hj1 || o > 0.0)) { jx1 = qx; jy1 = qy; hj1 = true; }
+        if (q > i1 && (!hk1 || o < 0.0)) { kx1 = qx; ky1 = qy; hk1 = true; }
+      }
+    }
+    // a strict vertex: the first or last point, or a strict turn of the
+    // chain's direction between the two extreme neighbours
+    vert[0] = i0 < m && (!hj0 || !hk0 || sg * cross3(jx0, jy0, x0, y0, kx0, ky0) > 0.0);
+    vert[1] = i1 < m && (!hj1 || !hk1 || sg * cross3(jx1, jy1, x1, y1, kx1, ky1) > 0.0);
+    ox[0] = x0; oy[0] = y0; oi[0] = i0 < m ? s_ui[w][i0] : 0u;
+    ox[1] = x1; oy[1] = y1; oi[1] = i1 < m ? s_ui[w][i1] : 0u;
+  }
+  __syncthreads();  // every read of a.key / b.pidx is done: the upper chain may overwrite them
+  if (w < 2) {
+    const uint64_t vm0 = __builtin_amdgcn_ballot_w64(vert[0]), vm1 = __builtin_amdgcn_ballot_w64(vert[1]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (vert[e]) {
+        const uint32_t pos = (e ? popc64(vm0) : 0u) + popc64((e ? vm1 : vm0) & lt);
+        if (w == 0) { sm.px[pos] = ox[e]; sm.py[pos] = oy[e]; sm.pi[pos] = oi[e]; }
+        else { sm.a.u.ux[pos] = ox[e]; sm.a.u.uy[pos] = oy[e]; sm.b.ui[pos] = oi[e]; }
+      }
+    }
+    if (lane == 0) s_n[w] = popc64(vm0) + popc64(vm1);
+  }
+  __syncthreads();
+  nl = s_n[0];
+  nu = s_n[1];
+  return true;
+}
+
 // Directions of the pre-filter polygon: 16 small-integer vectors in
 // counter-clockwise order (0, 22, 45, 68, 90, ... degrees). Dot products with
 // grid points stay below 7 * 2^20, exact in int32.
@@ -375,6 +562,10 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
   cnt = kept;
   __syncthreads();
   if (tm) CH_MARK(tm, 3);
+  if (kept >= 1 && kept <= 2 * kSmallChain && small_chains<T>(sm, kept, nl, nu)) {
+    if (tm) CH_MARK(tm, 6);
+    return nl + (nu > 2 ? nu - 2 : 0);
+  }
   bitonic_sort(sm.a.key, P2);
   if (tm) CH_MARK(tm, 4);
   // One entry per distinct coordinate, carrying the smallest index.
