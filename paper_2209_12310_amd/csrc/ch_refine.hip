@@ -6,9 +6,11 @@ namespace chk {
 
 // Batch (after the per-set octagons): one workgroup per set of at least
 // sample_min (and kBatchSample) points, sets taken with a fixed stride:
-// kBatchSample sample points, those strictly outside the set's octagon kept,
-// kBatchDirs directions, the polygon in the set's SamplePoly. Smaller sets,
-// and sets whose sample lies inside the octagon, get none.
+// chunks of kBatchSample sample points (one chunk per kBatchChunkPoints
+// points of the set, at most kBatchChunksMax, spread evenly over it), those
+// strictly outside the set's octagon kept, kBatchDirs directions, the
+// polygon in the set's SamplePoly. Smaller sets, and sets whose sample lies
+// inside the octagon, get none.
 __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict__ xy,
                                                          const uint64_t* __restrict__ off,
                                                          uint32_t nsets,
@@ -17,9 +19,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
                                                          SamplePoly* __restrict__ polys,
                                                          uint32_t sample_min) {
   static_assert(kBatchDirs == 2 * (uint32_t)kBlock, "a direction and its opposite per thread");
-  constexpr uint32_t E = kBatchSample / kBlock;  // sample points per thread
+  constexpr uint32_t E = kBatchSample / kBlock;  // sample points per thread and chunk
   __shared__ int2 sp[kBatchSample];
   __shared__ int32_t px[kBatchDirs], py[kBatchDirs];
+  __shared__ uint32_t s_tot;
   const bool bad_off = bh->bad_offsets != 0;
   int32_t a0, b0;
   direction(threadIdx.x, kBatchDirs, a0, b0);
@@ -31,38 +34,51 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
       if (threadIdx.x == 0) polys[s].nv = 0;
       continue;
     }
-    // Sample points strictly outside the set's octagon, compacted.
-    int2 v[E];
-    uint32_t outm = 0, nout = 0;
+    const uint32_t nch = (uint32_t)min<uint64_t>(max<uint64_t>(n / kBatchChunkPoints, 1), kBatchChunksMax);
+    const uint64_t ns = uint64_t(nch) * kBatchSample;
+    // running extremes of this thread's direction pair over the chunks
+    int32_t bmax = INT32_MIN, bmin = INT32_MAX;
+    int2 pmax = make_int2(0, 0), pmin = make_int2(0, 0);
+    uint32_t tot = 0;
+    for (uint32_t c = 0; c < nch; ++c) {
+      // Sample points strictly outside the set's octagon, compacted.
+      int2 v[E];
+      uint32_t outm = 0, nout = 0;
 #pragma unroll
-    for (uint32_t e = 0; e < E; ++e) {
-      const uint32_t q = threadIdx.x * E + e;
-      v[e] = grid_point(xy, base + (q * n) / kBatchSample);
-      const double x = (double)v[e].x * 0x1p-20, y = (double)v[e].y * 0x1p-20;
-      double mn = __builtin_inf();
+      for (uint32_t e = 0; e < E; ++e) {
+        const uint64_t q = uint64_t(c) * kBatchSample + threadIdx.x * E + e;
+        v[e] = grid_point(xy, base + (q * n) / ns);
+        const double x = (double)v[e].x * 0x1p-20, y = (double)v[e].y * 0x1p-20;
+        double mn = __builtin_inf();
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        mn = __builtin_fmin(mn, __builtin_fma(oct->A[i], x, __builtin_fma(oct->B[i], y, oct->C[i])));
-      if (mn < 0.0) { outm |= 1u << e; ++nout; }
+        for (int i = 0; i < 8; ++i)
+          mn = __builtin_fmin(mn, __builtin_fma(oct->A[i], x, __builtin_fma(oct->B[i], y, oct->C[i])));
+        if (mn < 0.0) { outm |= 1u << e; ++nout; }
+      }
+      __syncthreads();  // the previous chunk or set is done with the shared arrays
+      uint32_t m;
+      uint32_t pos = block_excl_scan(nout, m);
+#pragma unroll
+      for (uint32_t e = 0; e < E; ++e)
+        if (outm & (1u << e)) sp[pos++] = v[e];
+      __syncthreads();
+      tot += m;
+      if (m == 0) continue;
+      int32_t emax, emin;
+      uint32_t q0, q1;
+      dir_minmax(sp, m, a0, b0, emax, q0, emin, q1);
+      // earlier chunks win ties (the first occurrence, as within a chunk)
+      if (emax > bmax) { bmax = emax; pmax = sp[q0]; }
+      if (emin < bmin) { bmin = emin; pmin = sp[q1]; }
     }
-    __syncthreads();  // the previous set is done with the shared arrays
-    uint32_t m;
-    uint32_t pos = block_excl_scan(nout, m);
-#pragma unroll
-    for (uint32_t e = 0; e < E; ++e)
-      if (outm & (1u << e)) sp[pos++] = v[e];
-    __syncthreads();
-    if (m == 0) {
+    if (tot == 0) {
       if (threadIdx.x == 0) polys[s].nv = 0;
       continue;
     }
-    int32_t emax, emin;
-    uint32_t q0, q1;
-    dir_minmax(sp, m, a0, b0, emax, q0, emin, q1);
-    px[threadIdx.x] = sp[q0].x;
-    py[threadIdx.x] = sp[q0].y;
-    px[threadIdx.x + kBlock] = sp[q1].x;
-    py[threadIdx.x + kBlock] = sp[q1].y;
+    px[threadIdx.x] = pmax.x;
+    py[threadIdx.x] = pmax.y;
+    px[threadIdx.x + kBlock] = pmin.x;
+    py[threadIdx.x + kBlock] = pmin.y;
     __syncthreads();
     build_poly(px, py, kBatchDirs, &polys[s]);
   }
