@@ -1372,22 +1372,36 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
         drain(qn, 64);
       }
     };
-    for (uint32_t r = w; r < nrows; r += kWaves) {
-      const uint32_t q = r * 64 + lane;
-      const bool val = q < npairs;
-      const float4 v = val ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
-      const uint32_t g = a2 + 2 * q;
-      const bool in0 = (v.x > bxl) & (v.x < bxh) & (v.y > byl) & (v.y < byh);
-      const bool in1 = (v.z > bxl) & (v.z < bxh) & (v.w > byl) & (v.w < byh);
-      const bool need0 = val & !in0, need1 = val & !in1;
-      if (__ballot(need0 | need1)) {
-        bool t0 = need0, t1 = need1;
+    // kU rows of the wave per step (rows r + u kWaves), loaded together;
+    // then the cheap tests of all of them and one branch for the step.
+    for (uint32_t r = w; r < nrows; r += kU * kWaves) {
+      float4 v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t q = (r + u * kWaves) * 64 + lane;
+        v[u] = q < npairs ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      uint32_t tm = 0;  // bit 2u: first point of row u needs a test, 2u+1: the second
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool val = (r + u * kWaves) * 64 + lane < npairs;
+        const bool in0 = (v[u].x > bxl) & (v[u].x < bxh) & (v[u].y > byl) & (v[u].y < byh);
+        const bool in1 = (v[u].z > bxl) & (v[u].z < bxh) & (v[u].w > byl) & (v[u].w < byh);
+        bool t0 = val & !in0, t1 = val & !in1;
         if (use_sp) {
-          t0 = t0 & !in_inner(v.x, v.y, pcx, pcy, pr2, pos, pot);
-          t1 = t1 & !in_inner(v.z, v.w, pcx, pcy, pr2, pos, pot);
+          t0 = t0 & !in_inner(v[u].x, v[u].y, pcx, pcy, pr2, pos, pot);
+          t1 = t1 & !in_inner(v[u].z, v[u].w, pcx, pcy, pr2, pos, pot);
         }
-        push(t0, v.x, v.y, g - base);
-        push(t1, v.z, v.w, g + 1 - base);
+        tm |= (t0 ? 1u : 0u) << (2 * u);
+        tm |= (t1 ? 2u : 0u) << (2 * u);
+      }
+      if (__ballot(tm != 0)) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t g = a2 + 2 * ((r + u * kWaves) * 64 + lane);
+          push((tm >> (2 * u)) & 1u, v[u].x, v[u].y, g - base);
+          push((tm >> (2 * u)) & 2u, v[u].z, v[u].w, g + 1 - base);
+        }
       }
     }
     if (qn) drain(0, qn);

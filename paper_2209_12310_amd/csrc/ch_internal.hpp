@@ -87,7 +87,7 @@ constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
 constexpr uint32_t kSampleBlocks = kSampleN / kSamplePer;
 constexpr uint32_t kSampleMin = 1u << 17;  // ch_hull samples from this many points on
-constexpr uint32_t kBatchDirs = 512;       // batch: directions per set
+constexpr uint32_t kBatchDirs = 256;       // batch: directions per set
 constexpr uint32_t kBatchSample = 2048;    // batch: sample points per chunk
 constexpr uint32_t kBatchChunkPoints = 131072;  // batch: one sample chunk per this many points
 constexpr uint32_t kBatchChunksMax = 4;

@@ -18,14 +18,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
                                                          const SetState* __restrict__ sets,
                                                          SamplePoly* __restrict__ polys,
                                                          uint32_t sample_min) {
-  static_assert(kBatchDirs == 2 * (uint32_t)kBlock, "a direction and its opposite per thread");
+  // Thread t takes direction pair t % kPairs (a direction and its opposite)
+  // over half t / kPairs of each chunk's sample; the halves are combined.
+  constexpr uint32_t kPairs = kBatchDirs / 2;
+  static_assert(2 * kPairs == (uint32_t)kBlock, "two threads per direction pair");
   constexpr uint32_t E = kBatchSample / kBlock;  // sample points per thread and chunk
   __shared__ int2 sp[kBatchSample];
   __shared__ int32_t px[kBatchDirs], py[kBatchDirs];
-  __shared__ uint32_t s_tot;
+  __shared__ int32_t s_e[2][kPairs];
+  __shared__ int2 s_p[2][kPairs];
   const bool bad_off = bh->bad_offsets != 0;
+  const uint32_t pr = threadIdx.x % kPairs, half = threadIdx.x / kPairs;
   int32_t a0, b0;
-  direction(threadIdx.x, kBatchDirs, a0, b0);
+  direction(pr, kBatchDirs, a0, b0);
   for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
     const uint64_t base = off[s];
     const uint64_t n = bad_off ? 0 : off[s + 1] - base;
@@ -37,6 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
     const uint32_t nch = (uint32_t)min<uint64_t>(max<uint64_t>(n / kBatchChunkPoints, 1), kBatchChunksMax);
     const uint64_t ns = uint64_t(nch) * kBatchSample;
     // running extremes of this thread's direction pair over the chunks
+    // (kept by the threads of half 0)
     int32_t bmax = INT32_MIN, bmin = INT32_MAX;
     int2 pmax = make_int2(0, 0), pmin = make_int2(0, 0);
     uint32_t tot = 0;
@@ -64,21 +70,41 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
       __syncthreads();
       tot += m;
       if (m == 0) continue;
-      int32_t emax, emin;
-      uint32_t q0, q1;
-      dir_minmax(sp, m, a0, b0, emax, q0, emin, q1);
-      // earlier chunks win ties (the first occurrence, as within a chunk)
-      if (emax > bmax) { bmax = emax; pmax = sp[q0]; }
-      if (emin < bmin) { bmin = emin; pmin = sp[q1]; }
+      const uint32_t h0 = half * (m / 2), h1 = half ? m : m / 2;
+      int32_t emax = INT32_MIN, emin = INT32_MAX;
+      uint32_t q0 = h0, q1 = h0;
+      if (h1 > h0) {
+        dir_minmax(sp + h0, h1 - h0, a0, b0, emax, q0, emin, q1);
+        q0 += h0;
+        q1 += h0;
+      }
+      if (half) {
+        s_e[0][pr] = emax;
+        s_e[1][pr] = emin;
+        s_p[0][pr] = sp[q0];
+        s_p[1][pr] = sp[q1];
+      }
+      __syncthreads();
+      if (!half) {
+        // the first half wins ties (the first occurrence in the chunk), and
+        // earlier chunks win ties over later ones
+        int2 cmax = sp[q0], cmin = sp[q1];
+        if (s_e[0][pr] > emax) { emax = s_e[0][pr]; cmax = s_p[0][pr]; }
+        if (s_e[1][pr] < emin) { emin = s_e[1][pr]; cmin = s_p[1][pr]; }
+        if (emax > bmax) { bmax = emax; pmax = cmax; }
+        if (emin < bmin) { bmin = emin; pmin = cmin; }
+      }
     }
     if (tot == 0) {
       if (threadIdx.x == 0) polys[s].nv = 0;
       continue;
     }
-    px[threadIdx.x] = pmax.x;
-    py[threadIdx.x] = pmax.y;
-    px[threadIdx.x + kBlock] = pmin.x;
-    py[threadIdx.x + kBlock] = pmin.y;
+    if (!half) {
+      px[pr] = pmax.x;
+      py[pr] = pmax.y;
+      px[pr + kPairs] = pmin.x;
+      py[pr + kPairs] = pmin.y;
+    }
     __syncthreads();
     build_poly(px, py, kBatchDirs, &polys[s]);
   }
