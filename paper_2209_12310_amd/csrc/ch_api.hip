@@ -56,8 +56,8 @@ hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
-                                    uint32_t grid, uint32_t sample_min, uint32_t sample_grid,
-                                    hipStream_t st);
+                                    Rec* cand, uint32_t grid, uint32_t sample_min,
+                                    uint32_t sample_grid, hipStream_t st);
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
@@ -370,7 +370,7 @@ ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
     ProfScope ps(ctx, st, "batch_filter");
     e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
                                  at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles), recA,
-                                 p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 2, st);
+                                 recB, p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 2, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
   {

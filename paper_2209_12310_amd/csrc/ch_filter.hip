@@ -1209,71 +1209,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restric
     for (int k = 0; k < 8; ++k) ss.key[k] = 0ull;
     ss.bad = 0;
     ss.done = 0;
+    ss.ncand = 0;
     for (int r = 0; r <= kBatchRounds; ++r) ss.cnt[r] = 0;
   }
   if (threadIdx.x == 0) {
     bh->ntiles = total;
     bh->bad_offsets = bad ? 1u : 0u;
     for (int r = 0; r <= kBatchRounds; ++r) bh->nround[r] = 0;
-  }
-}
-
-// Iterates the points of [a, b) of a 16-byte aligned point array, two at a
-// time where possible: f(x, y, g) for every point g, spread over the block.
-template <class F>
-__device__ __forceinline__ void for_points(const float* __restrict__ xy, uint32_t a, uint32_t b,
-                                           F&& f) {
-  const uint32_t a2 = a + (a & 1u);
-  const uint32_t npairs = b > a2 ? (b - a2) >> 1 : 0;
-  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * (size_t)a2);
-  uint32_t p = threadIdx.x;
-  for (; p + 3 * kBlock < npairs; p += 4 * kBlock) {
-    float4 v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = ld_stream(&p4[p + u * kBlock]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t g = a2 + 2 * (p + u * kBlock);
-      f(v[u].x, v[u].y, g);
-      f(v[u].z, v[u].w, g + 1);
-    }
-  }
-  for (; p < npairs; p += kBlock) {
-    const float4 v = ld_stream(&p4[p]);
-    const uint32_t g = a2 + 2 * p;
-    f(v.x, v.y, g);
-    f(v.z, v.w, g + 1);
-  }
-  if (threadIdx.x == 0) {
-    if ((a & 1u) && a < b) f(xy[2 * (size_t)a], xy[2 * (size_t)a + 1], a);
-    const uint32_t last = a2 + 2 * npairs;
-    if (last < b) f(xy[2 * (size_t)last], xy[2 * (size_t)last + 1], last);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_batch_reduce(const float* __restrict__ xy,
-                                                         const BatchHdr* __restrict__ bh,
-                                                         const SetTile* __restrict__ tiles,
-                                                         SetState* __restrict__ sets) {
-  const uint32_t ntiles = bh->ntiles;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const SetTile st = tiles[t];
-    Keys k;
-    keys_init(k);
-    bool bad = false;
-    for_points(xy, st.begin, st.end, [&](float x, float y, uint32_t) { keys_add(k, x, y, bad); });
-    const uint64_t badmask = __ballot(bad);
-    block_keys(k);
-    if (threadIdx.x == 0) {
-      SetState& ss = sets[st.set];
-      const double mx[4] = {k.mxE, k.mxN, k.mxNE, k.mxSE};
-      const double mn[4] = {k.mnE, k.mnN, k.mnNE, k.mnSE};
-      for (int i = 0; i < 4; ++i) {
-        atomicMax((unsigned long long*)&ss.key[i], (unsigned long long)enc_f64(mx[i]));
-        atomicMax((unsigned long long*)&ss.key[4 + i], (unsigned long long)enc_f64(-mn[i]));
-      }
-    }
-    if ((threadIdx.x & 63) == 0 && badmask) atomicOr(&sets[st.set].bad, 1u);
   }
 }
 
@@ -1294,15 +1236,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_octagon(const uint64_t* __rest
   octagon_wave(k, ss.oct, ss.vidx, ss.bad);
 }
 
-// Pass 2 of a tile: exact octagon test, survivors appended as records with
-// set-local indices to recs[off[set] + ...] (one atomic per wave and row).
-__global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict__ xy,
-                                                         const uint64_t* __restrict__ off,
-                                                         const BatchHdr* __restrict__ bh,
-                                                         const SetTile* __restrict__ tiles,
-                                                         SetState* __restrict__ sets,
-                                                         const SamplePoly* __restrict__ polys,
-                                                         Rec* __restrict__ recs) {
+// The single read of a tile (pass 1 and the polygon test, as k_pass_hull
+// for one set): with the set's sample polygon, the grid check of every point
+// (fractional parts) and the inner-region test; points outside the region
+// get their keys and the exact polygon test through the wave's queue, and
+// those not strictly inside become candidate records in the set's slice of
+// `cand` (set-local indices). Without a polygon (small sets) every point
+// gets its keys and becomes a candidate. The tile's keys go into the set's
+// with 64-bit atomic max on an order-preserving encoding.
+__global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__ xy,
+                                                       const uint64_t* __restrict__ off,
+                                                       const BatchHdr* __restrict__ bh,
+                                                       const SetTile* __restrict__ tiles,
+                                                       SetState* __restrict__ sets,
+                                                       const SamplePoly* __restrict__ polys,
+                                                       Rec* __restrict__ cand) {
   __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
@@ -1312,9 +1260,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const SetTile st = tiles[t];
     SetState& ss = sets[st.set];
-    const Octagon* __restrict__ o = &ss.oct;
-    if (o->status != 0) continue;  // block-uniform
-    const float bxl = o->box[0], bxh = o->box[1], byl = o->box[2], byh = o->box[3];
     // The set's sample polygon, if it has one (block-uniform).
     const SamplePoly* __restrict__ sp = &polys[st.set];
     const uint32_t pnv = min(sp->nv, (uint32_t)kPolyMax);
@@ -1336,34 +1281,39 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
     const uint32_t npairs = b > a2 ? (b - a2) >> 1 : 0;
     const uint32_t nrows = (npairs + 63) / 64;
     const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * (size_t)a2);
-    // Exact tests through the wave's queue (see kQueue); survivors are
-    // appended to the set's slice with one atomic per 64 tests.
+    Keys k;
+    keys_init(k);
+    bool bad = false;
+    float frac = 0.f;  // largest fractional part of a scaled coordinate (inner points)
     uint32_t qn = 0;
+    // Candidates of the wave's ballot, appended with one atomic.
+    auto emit = [&](bool keep, float x, float y, uint32_t gl) {
+      const uint64_t bk = __ballot(keep);
+      if (!bk) return;
+      uint32_t p = 0;
+      if (lane == 0) p = atomicAdd(&ss.ncand, popc64(bk));
+      p = __shfl(p, 0) + popc64(bk & lt);
+      if (keep) cand[base + p] = make_payload<Rec>(gl, x, y);
+    };
+    // Queued points (outside the inner region): keys, then the exact test.
     auto drain = [&](uint32_t qb, uint32_t cnt) {
       float x = 0.f, y = 0.f;
       uint32_t gl = 0;
-      if (lane < (int)cnt) { x = s_qx[w][qb + lane]; y = s_qy[w][qb + lane]; gl = s_qg[w][qb + lane]; }
-      wave_sync();
-      bool keep = false;
       if (lane < (int)cnt) {
-        keep = classify<false>(x, y, gl, o, ss.vidx).keep;
-        if (keep && use_sp)
-          keep = !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+        x = s_qx[w][qb + lane]; y = s_qy[w][qb + lane]; gl = s_qg[w][qb + lane];
+        keys_add(k, x, y, bad);
       }
-      const uint64_t bk = __ballot(keep);
-      if (bk) {
-        uint32_t pos = 0;
-        if (lane == 0) pos = atomicAdd(&ss.cnt[0], popc64(bk));
-        pos = __shfl(pos, 0) + popc64(bk & lt);
-        if (keep) recs[base + pos] = make_payload<Rec>(gl, x, y);
-      }
+      wave_sync();
+      const bool keep = lane < (int)cnt &&
+                        !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+      emit(keep, x, y, gl);
     };
     auto push = [&](bool qq, float x, float y, uint32_t gl) {
       const uint64_t m = __ballot(qq);
       if (!m) return;
       if (qq) {
-        const uint32_t pos = qn + popc64(m & lt);
-        s_qx[w][pos] = x; s_qy[w][pos] = y; s_qg[w][pos] = gl;
+        const uint32_t p = qn + popc64(m & lt);
+        s_qx[w][p] = x; s_qy[w][p] = y; s_qg[w][p] = gl;
       }
       qn += popc64(m);
       wave_sync();
@@ -1372,8 +1322,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
         drain(qn, 64);
       }
     };
-    // kU rows of the wave per step (rows r + u kWaves), loaded together;
-    // then the cheap tests of all of them and one branch for the step.
+    // kU rows of the wave per step (rows r + u kWaves), loaded together.
     for (uint32_t r = w; r < nrows; r += kU * kWaves) {
       float4 v[kU];
 #pragma unroll
@@ -1381,30 +1330,44 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
         const uint32_t q = (r + u * kWaves) * 64 + lane;
         v[u] = q < npairs ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      uint32_t tm = 0;  // bit 2u: first point of row u needs a test, 2u+1: the second
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const bool val = (r + u * kWaves) * 64 + lane < npairs;
-        const bool in0 = (v[u].x > bxl) & (v[u].x < bxh) & (v[u].y > byl) & (v[u].y < byh);
-        const bool in1 = (v[u].z > bxl) & (v[u].z < bxh) & (v[u].w > byl) & (v[u].w < byh);
-        bool t0 = val & !in0, t1 = val & !in1;
-        if (use_sp) {
-          t0 = t0 & !in_inner(v[u].x, v[u].y, pcx, pcy, pr2, pos, pot);
-          t1 = t1 & !in_inner(v[u].z, v[u].w, pcx, pcy, pr2, pos, pot);
-        }
-        tm |= (t0 ? 1u : 0u) << (2 * u);
-        tm |= (t1 ? 2u : 0u) << (2 * u);
-      }
-      if (__ballot(tm != 0)) {
+      if (use_sp) {
+        uint32_t tm = 0;  // bit 2u: first point of row u is queued, 2u+1: the second
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+          const bool val = (r + u * kWaves) * 64 + lane < npairs;
+          frac = __builtin_fmaxf(frac, __builtin_fmaxf(__builtin_amdgcn_fractf(v[u].x * kGridF),
+                                                       __builtin_amdgcn_fractf(v[u].y * kGridF)));
+          frac = __builtin_fmaxf(frac, __builtin_fmaxf(__builtin_amdgcn_fractf(v[u].z * kGridF),
+                                                       __builtin_amdgcn_fractf(v[u].w * kGridF)));
+          const bool t0 = val & !in_inner(v[u].x, v[u].y, pcx, pcy, pr2, pos, pot);
+          const bool t1 = val & !in_inner(v[u].z, v[u].w, pcx, pcy, pr2, pos, pot);
+          tm |= (t0 ? 1u : 0u) << (2 * u);
+          tm |= (t1 ? 2u : 0u) << (2 * u);
+        }
+        if (__ballot(tm != 0)) {
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const uint32_t g = a2 + 2 * ((r + u * kWaves) * 64 + lane);
+            push((tm >> (2 * u)) & 1u, v[u].x, v[u].y, g - base);
+            push((tm >> (2 * u)) & 2u, v[u].z, v[u].w, g + 1 - base);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const bool val = (r + u * kWaves) * 64 + lane < npairs;
+          if (val) {
+            keys_add(k, v[u].x, v[u].y, bad);
+            keys_add(k, v[u].z, v[u].w, bad);
+          }
           const uint32_t g = a2 + 2 * ((r + u * kWaves) * 64 + lane);
-          push((tm >> (2 * u)) & 1u, v[u].x, v[u].y, g - base);
-          push((tm >> (2 * u)) & 2u, v[u].z, v[u].w, g + 1 - base);
+          emit(val, v[u].x, v[u].y, g - base);
+          emit(val, v[u].z, v[u].w, g + 1 - base);
         }
       }
     }
     if (qn) drain(0, qn);
+    bad |= frac != 0.f;
     if (threadIdx.x == 0) {
       const uint32_t last = a2 + 2 * npairs;
       uint32_t singles[2];
@@ -1414,12 +1377,59 @@ __global__ __launch_bounds__(kBlock) void k_batch_filter(const float* __restrict
       for (int i = 0; i < ns; ++i) {
         const uint32_t g = singles[i];
         const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
-        if (classify<false>(x, y, g - base, o, ss.vidx).keep &&
-            !(use_sp && poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF)))) {
-          const uint32_t pos = atomicAdd(&ss.cnt[0], 1u);
-          recs[base + pos] = make_payload<Rec>(g - base, x, y);
-        }
+        keys_add(k, x, y, bad);
+        if (!use_sp ||
+            !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF)))
+          cand[base + atomicAdd(&ss.ncand, 1u)] = make_payload<Rec>(g - base, x, y);
       }
+    }
+    const uint64_t badmask = __ballot(bad);
+    block_keys(k);
+    if (threadIdx.x == 0) {
+      const double mx[4] = {k.mxE, k.mxN, k.mxNE, k.mxSE};
+      const double mn[4] = {k.mnE, k.mnN, k.mnNE, k.mnSE};
+      for (int i = 0; i < 4; ++i) {
+        atomicMax((unsigned long long*)&ss.key[i], (unsigned long long)enc_f64(mx[i]));
+        atomicMax((unsigned long long*)&ss.key[4 + i], (unsigned long long)enc_f64(-mn[i]));
+      }
+    }
+    if (lane == 0 && badmask) atomicOr(&ss.bad, 1u);
+  }
+}
+
+// After the per-set octagons: the octagon test of every set's candidates
+// (one workgroup per set at a time), survivors appended as records to the
+// set's slice of `surv`, their count in cnt[0].
+__global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restrict__ off,
+                                                       uint32_t nsets,
+                                                       const BatchHdr* __restrict__ bh,
+                                                       SetState* __restrict__ sets,
+                                                       const Rec* __restrict__ cand,
+                                                       Rec* __restrict__ surv) {
+  if (bh->bad_offsets) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
+    SetState& ss = sets[s];
+    const Octagon* __restrict__ o = &ss.oct;
+    if (off[s + 1] <= off[s] || o->status != 0) continue;
+    const uint32_t base = (uint32_t)off[s];
+    const uint32_t m = ss.ncand;
+    for (uint32_t i0 = threadIdx.x - lane; i0 < m; i0 += kBlock) {
+      const uint32_t i = i0 + lane;
+      Rec r{};
+      bool keep = false;
+      if (i < m) {
+        r = cand[base + i];
+        keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
+                               ss.vidx).keep;
+      }
+      const uint64_t bk = __ballot(keep);
+      if (!bk) continue;
+      uint32_t p = 0;
+      if (lane == 0) p = atomicAdd(&ss.cnt[0], popc64(bk));
+      p = __shfl(p, 0) + popc64(bk & lt);
+      if (keep) surv[base + p] = r;
     }
   }
 }
@@ -1510,23 +1520,24 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 namespace chk {
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, uint32_t nsets,
-                               const BatchHdr* bh, const SetState* sets, SamplePoly* polys,
-                               uint32_t sample_min, uint32_t grid, hipStream_t st);
+                               const BatchHdr* bh, SamplePoly* polys, uint32_t sample_min,
+                               uint32_t grid, hipStream_t st);
 
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
-                                    uint32_t grid, uint32_t sample_min, uint32_t sample_grid,
-                                    hipStream_t st) {
+                                    Rec* cand, uint32_t grid, uint32_t sample_min,
+                                    uint32_t sample_grid, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
                      sets, tiles);
-  hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(kBlock), 0, st, xy, bh, tiles, sets);
+  hipError_t e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
+                     cand);
   hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
                      nsets, bh, sets);
-  hipError_t e = launch_batch_sample(xy, off, nsets, bh, sets, polys, sample_min, sample_grid, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_filter, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets,
-                     polys, recs);
+  hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets, cand,
+                     recs);
   return hipGetLastError();
 }
 

@@ -182,7 +182,7 @@ struct SetState {
   uint32_t done;       // hull written
   uint32_t cnt[kBatchRounds + 1];  // candidates after the filter / after round r
   uint32_t vidx[8];    // smallest index per octagon slot (kept for the shared classifier)
-  uint32_t pad[16 - 2 - (kBatchRounds + 1) - 8];
+  uint32_t ncand;       // candidate records of the single read (fused pass)
   Octagon oct;
 };
 

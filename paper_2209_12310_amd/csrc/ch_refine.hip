@@ -4,25 +4,22 @@
 
 namespace chk {
 
-// Batch (after the per-set octagons): one workgroup per set of at least
+// Batch (before the single read): one workgroup per set of at least
 // sample_min (and kBatchSample) points, sets taken with a fixed stride:
 // chunks of kBatchSample sample points (one chunk per kBatchChunkPoints
-// points of the set, at most kBatchChunksMax, spread evenly over it), those
-// strictly outside the set's octagon kept, kBatchDirs directions, the
-// polygon in the set's SamplePoly. Smaller sets, and sets whose sample lies
-// inside the octagon, get none.
+// points of the set, at most kBatchChunksMax, spread evenly over it),
+// kBatchDirs directions, the polygon in the set's SamplePoly. Smaller sets
+// get none.
 __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict__ xy,
                                                          const uint64_t* __restrict__ off,
                                                          uint32_t nsets,
                                                          const BatchHdr* __restrict__ bh,
-                                                         const SetState* __restrict__ sets,
                                                          SamplePoly* __restrict__ polys,
                                                          uint32_t sample_min) {
   // Thread t takes direction pair t % kPairs (a direction and its opposite)
   // over half t / kPairs of each chunk's sample; the halves are combined.
   constexpr uint32_t kPairs = kBatchDirs / 2;
   static_assert(2 * kPairs == (uint32_t)kBlock, "two threads per direction pair");
-  constexpr uint32_t E = kBatchSample / kBlock;  // sample points per thread and chunk
   __shared__ int2 sp[kBatchSample];
   __shared__ int32_t px[kBatchDirs], py[kBatchDirs];
   __shared__ int32_t s_e[2][kPairs];
@@ -34,8 +31,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
   for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
     const uint64_t base = off[s];
     const uint64_t n = bad_off ? 0 : off[s + 1] - base;
-    const Octagon* __restrict__ oct = &sets[s].oct;
-    if (n < sample_min || n < kBatchSample || oct->status != 0) {
+    if (n < sample_min || n < kBatchSample) {
       if (threadIdx.x == 0) polys[s].nv = 0;
       continue;
     }
@@ -45,31 +41,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
     // (kept by the threads of half 0)
     int32_t bmax = INT32_MIN, bmin = INT32_MAX;
     int2 pmax = make_int2(0, 0), pmin = make_int2(0, 0);
-    uint32_t tot = 0;
     for (uint32_t c = 0; c < nch; ++c) {
-      // Sample points strictly outside the set's octagon, compacted.
-      int2 v[E];
-      uint32_t outm = 0, nout = 0;
-#pragma unroll
-      for (uint32_t e = 0; e < E; ++e) {
-        const uint64_t q = uint64_t(c) * kBatchSample + threadIdx.x * E + e;
-        v[e] = grid_point(xy, base + (q * n) / ns);
-        const double x = (double)v[e].x * 0x1p-20, y = (double)v[e].y * 0x1p-20;
-        double mn = __builtin_inf();
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          mn = __builtin_fmin(mn, __builtin_fma(oct->A[i], x, __builtin_fma(oct->B[i], y, oct->C[i])));
-        if (mn < 0.0) { outm |= 1u << e; ++nout; }
-      }
       __syncthreads();  // the previous chunk or set is done with the shared arrays
-      uint32_t m;
-      uint32_t pos = block_excl_scan(nout, m);
-#pragma unroll
-      for (uint32_t e = 0; e < E; ++e)
-        if (outm & (1u << e)) sp[pos++] = v[e];
+      for (uint32_t q = threadIdx.x; q < kBatchSample; q += kBlock)
+        sp[q] = grid_point(xy, base + ((uint64_t(c) * kBatchSample + q) * n) / ns);
       __syncthreads();
-      tot += m;
-      if (m == 0) continue;
+      const uint32_t m = kBatchSample;
       const uint32_t h0 = half * (m / 2), h1 = half ? m : m / 2;
       int32_t emax = INT32_MIN, emin = INT32_MAX;
       uint32_t q0 = h0, q1 = h0;
@@ -94,10 +71,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
         if (emax > bmax) { bmax = emax; pmax = cmax; }
         if (emin < bmin) { bmin = emin; pmin = cmin; }
       }
-    }
-    if (tot == 0) {
-      if (threadIdx.x == 0) polys[s].nv = 0;
-      continue;
     }
     if (!half) {
       px[pr] = pmax.x;
@@ -190,10 +163,10 @@ hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, Sample
 }
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, uint32_t nsets,
-                               const BatchHdr* bh, const SetState* sets, SamplePoly* polys,
-                               uint32_t sample_min, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_sample, dim3(grid), dim3(kBlock), 0, st, xy, off, nsets, bh, sets,
-                     polys, sample_min);
+                               const BatchHdr* bh, SamplePoly* polys, uint32_t sample_min,
+                               uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_sample, dim3(grid), dim3(kBlock), 0, st, xy, off, nsets, bh, polys,
+                     sample_min);
   return hipGetLastError();
 }
 

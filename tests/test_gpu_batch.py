@@ -94,6 +94,27 @@ def test_domain_error_in_one_set(ctx):
         assert np.array_equal(idx[off[s]: off[s] + cnt[s]], want)
 
 
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_domain_error_inside_sample_polygon(ctx, where):
+    """Off-grid values deep inside large sets (inside their sample polygon's
+    inner region, where the single read only runs the grid check) and at
+    odd tile ends give those sets a domain error; the other sets keep their
+    hulls."""
+    _say(f"batch domain error inside the polygon, {where}")
+    sets = [workloads.normal(70001 + 3 * s, 40 + s) for s in range(4)]
+    for s in (1, 3):
+        n = sets[s].shape[0]
+        i = {"first": 0, "middle": n // 2, "last": n - 1}[where]
+        sets[s] = sets[s].copy()
+        sets[s][i] = (np.float32(0.5 + 2.0 ** -23), np.float32(0.5))
+    off, idx, cnt = _run(ctx, sets)
+    assert cnt[1] == 0xFFFFFFFF and cnt[3] == 0xFFFFFFFF
+    for s in (0, 2):
+        want = oracle.hull(sets[s])
+        assert cnt[s] == len(want)
+        assert np.array_equal(idx[off[s]: off[s] + cnt[s]], want)
+
+
 def test_invalid_offsets(ctx):
     _say("batch invalid offsets")
     import torch
