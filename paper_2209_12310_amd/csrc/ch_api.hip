@@ -370,7 +370,7 @@ ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
     ProfScope ps(ctx, st, "batch_filter");
     e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
                                  at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles), recA,
-                                 recB, p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 2, st);
+                                 recB, p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 4, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
   {

@@ -1322,14 +1322,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
         drain(qn, 64);
       }
     };
-    // kU rows of the wave per step (rows r + u kWaves), loaded together.
-    for (uint32_t r = w; r < nrows; r += kU * kWaves) {
-      float4 v[kU];
+    // kU rows of the wave per step (rows r + u kWaves), loaded together;
+    // the next step's rows are requested before this step is tested.
+    auto load = [&](float4 (&dst)[kU], uint32_t r) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const uint32_t q = (r + u * kWaves) * 64 + lane;
-        v[u] = q < npairs ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        dst[u] = q < npairs ? ld_stream(&p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
+    };
+    float4 v[kU], nx[kU];
+    if ((uint32_t)w < nrows) load(v, w);
+    for (uint32_t r = w; r < nrows; r += kU * kWaves) {
+      const uint32_t rn = r + kU * kWaves;
+      if (rn < nrows) load(nx, rn);
       if (use_sp) {
         uint32_t tm = 0;  // bit 2u: first point of row u is queued, 2u+1: the second
 #pragma unroll
@@ -1365,6 +1371,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
           emit(val, v[u].z, v[u].w, g + 1 - base);
         }
       }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) v[u] = nx[u];
     }
     if (qn) drain(0, qn);
     bad |= frac != 0.f;
@@ -1415,21 +1423,36 @@ __global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restric
     if (off[s + 1] <= off[s] || o->status != 0) continue;
     const uint32_t base = (uint32_t)off[s];
     const uint32_t m = ss.ncand;
-    for (uint32_t i0 = threadIdx.x - lane; i0 < m; i0 += kBlock) {
-      const uint32_t i = i0 + lane;
-      Rec r{};
-      bool keep = false;
-      if (i < m) {
-        r = cand[base + i];
-        keep = classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, o,
-                               ss.vidx).keep;
+    // kR records per lane and step, loaded together; one reservation per
+    // wave and step.
+    constexpr int kR = 8;
+    for (uint32_t i0 = (threadIdx.x - lane) * kR; i0 < m; i0 += kBlock * kR) {
+      Rec r[kR];
+      uint64_t bk[kR];
+      uint32_t tot = 0;
+#pragma unroll
+      for (int j = 0; j < kR; ++j) {
+        const uint32_t i = i0 + j * 64 + lane;
+        r[j] = i < m ? cand[base + i] : Rec{};
       }
-      const uint64_t bk = __ballot(keep);
-      if (!bk) continue;
+#pragma unroll
+      for (int j = 0; j < kR; ++j) {
+        const uint32_t i = i0 + j * 64 + lane;
+        const bool keep = i < m && classify<false>((float)r[j].x * (1.0f / kGridF),
+                                                   (float)r[j].y * (1.0f / kGridF), r[j].i, o,
+                                                   ss.vidx).keep;
+        bk[j] = __ballot(keep);
+        tot += popc64(bk[j]);
+      }
+      if (!tot) continue;
       uint32_t p = 0;
-      if (lane == 0) p = atomicAdd(&ss.cnt[0], popc64(bk));
-      p = __shfl(p, 0) + popc64(bk & lt);
-      if (keep) surv[base + p] = r;
+      if (lane == 0) p = atomicAdd(&ss.cnt[0], tot);
+      p = __shfl(p, 0);
+#pragma unroll
+      for (int j = 0; j < kR; ++j) {
+        if ((bk[j] >> lane) & 1ull) surv[base + p + popc64(bk[j] & lt)] = r[j];
+        p += popc64(bk[j]);
+      }
     }
   }
 }
