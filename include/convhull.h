@@ -134,7 +134,11 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
  * records of the refined filter's single read (0 when it was not used: below
  * 131072 points, or no usable sample polygon); the records left after the
  * octagon test (the hull pass's input); the tile-hull rounds; whether the
- * large-hull path ran; h. Diagnostics only. */
+ * large-hull path ran; h; and how the single read ran: bit 0 set when it
+ * used the sample polygon, bit 1 when its inner region was the octagon (else
+ * the disc), bit 2 when it streamed on its whole grid (many points outside
+ * the inner region) rather than one workgroup per CU; 0 without a single
+ * read. Diagnostics only. */
 typedef struct {
   uint32_t n;
   uint32_t candidates;
@@ -142,6 +146,7 @@ typedef struct {
   uint32_t rounds;
   uint32_t large_path;
   uint32_t h;
+  uint32_t single_read;
 } ch_hull_info;
 ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out);
 

@@ -38,7 +38,7 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
                              const SamplePoly* gate, const Rec* cand, const void* scratch,
-                             uint32_t* ncand_out, hipStream_t st);
+                             uint32_t* ncand_out, uint32_t* mode_out, hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -244,7 +244,7 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
     ProfScope p(ctx, st, fused ? "cand_filter" : "filter_compact");
     if (surv_rec)
       e = launch_filter_rec(d_xy, n, head, hdr, g1, surv_rec, count_out, poly, cand, scratch,
-                            &res->ncand, st);
+                            &res->ncand, &res->mode, st);
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);
@@ -561,6 +561,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   ch_hull_info info{};
   info.n = n;
   info.candidates = hres->ncand;
+  info.single_read = hres->mode;
   info.survivors = hres->cin;
   bool large = false;
   int round = 0;

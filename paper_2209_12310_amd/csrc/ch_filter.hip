@@ -752,7 +752,10 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
                                                         const SamplePoly* __restrict__ gate,
                                                         const Rec* __restrict__ cand,
                                                         const uint32_t* __restrict__ cand_count,
-                                                        uint32_t* __restrict__ ncand_out) {
+                                                        uint32_t* __restrict__ ncand_out,
+                                                        const uint32_t* __restrict__ mode_in,
+                                                        uint32_t* __restrict__ mode_out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mode_out = mode_in ? *mode_in : 0u;
   // After a fused pass with a usable sample polygon only its candidates need
   // the octagon test; otherwise this is the second read of the points.
   if (gate && gate->nv >= 3) {
@@ -963,6 +966,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
     for (int i = 0; i < kWaves; ++i) est += s_est[i];
     if (est * kWideRatio <= kBlock * kEstPer) act = min(narrow_blocks, gridDim.x);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    sd->mode = (use_sp ? 1u : 0u) | (use_oct ? 2u : 0u) | (use_sp && act == gridDim.x ? 4u : 0u);
   if (blockIdx.x >= act) {
     if (threadIdx.x == 0) {
       Keys e;
@@ -1526,10 +1531,11 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
                              const SamplePoly* gate, const Rec* cand, const void* scratch,
-                             uint32_t* ncand_out, hipStream_t st) {
-  const uint32_t* cc = scratch ? &static_cast<const SampleDirs*>(scratch)->cand : nullptr;
+                             uint32_t* ncand_out, uint32_t* mode_out, hipStream_t st) {
+  const SampleDirs* sd = static_cast<const SampleDirs*>(scratch);
   hipLaunchKernelGGL(k_filter_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, surv,
-                     count_out, gate, cand, cc, ncand_out);
+                     count_out, gate, cand, sd ? &sd->cand : nullptr, ncand_out,
+                     sd ? &sd->mode : nullptr, mode_out);
   return hipGetLastError();
 }
 

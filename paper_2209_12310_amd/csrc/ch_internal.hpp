@@ -64,7 +64,8 @@ struct Result {
   uint32_t ucount;
   uint32_t cin;        // input count of the latest hull round
   uint32_t ncand;      // candidate records of the fused pass (0 without one)
-  uint32_t pad[2];
+  uint32_t mode;       // how the fused pass ran (ch_hull_info.single_read)
+  uint32_t pad;
   uint32_t round_cnt[kMaxRounds];   // records written by round r (index r+1 = output of round r)
   uint32_t round_tile[kMaxRounds];  // dynamic tile counter of round r
   uint32_t win_cnt[4];              // window-round outputs (lower, upper) per parity

@@ -399,7 +399,8 @@ struct SampleDirs {
   int32_t vx[kPolyMax], vy[kPolyMax];  // extreme sample point per direction
   uint32_t arrive;
   uint32_t cand;       // candidate records written by the fused pass
-  uint32_t pad[62];
+  uint32_t mode;       // how the fused pass ran (bits: polygon, octagon, whole grid)
+  uint32_t pad[61];
   uint32_t lut[kLutBins];              // wedge table of the polygon (see build_poly)
   int4 part[kSampleBlocks][kPolyMax];  // (dot product, x, y, 0)
 };

@@ -234,6 +234,13 @@ def test_full_size(ctx, name):
     _say(f"full {name}: gpu (survivors={want_s.size}, h={want_h.size})")
     got_h = ctx.hull(t)
     assert np.array_equal(got_h, want_h)
+    # the single read used the sample polygon, with the inner region and
+    # grid its data call for (bit 1: octagon, else disc; bit 2: whole grid)
+    mode = ctx.last_hull_info()["single_read"]
+    assert mode & 1
+    assert bool(mode & 2) == (name == "uniform_1e8"), mode
+    if name != "uniform_1e8":
+        assert bool(mode & 4) == (name == "annulus_1e8"), mode
     fr = ctx.filter(t, octagon=True)
     assert fr.count == want_s.size
     assert np.array_equal(fr.survivors.cpu().numpy().view(np.uint32), want_s)

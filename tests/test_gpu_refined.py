@@ -126,17 +126,19 @@ def test_domain_error_at_sampled_points(ctx, where):
         ctx.hull(_dev(xy))
 
 
+@pytest.mark.parametrize("kind", ["normal", "uniform"])
 @pytest.mark.parametrize("where", [1, 4097, "middle", "second_last", "last"])
-def test_domain_error_inside_polygon(ctx, where):
+def test_domain_error_inside_polygon(ctx, where, kind):
     """Off-grid values deep inside the data (inside the sample polygon's
-    disc, where the single-read pass skips the extreme keys) still give the
-    call's domain error: half a grid step and a sixteenth of one."""
+    inner region -- its disc for normal data, its octagon for the uniform
+    square -- where the single-read pass skips the extreme keys) still give
+    the call's domain error: half a grid step and a sixteenth of one."""
     import paper_2209_12310_amd as ch
     n = SAMPLE_MIN + 999
-    base = workloads.normal(n, 95)
+    base = workloads.by_kind(kind, n, 95)
     i = {"middle": n // 2, "second_last": n - 2, "last": n - 1}.get(where, where)
     for off in (2.0 ** -21, 2.0 ** -24):
-        _say(f"refined domain error inside the polygon at {where}, offset {off}")
+        _say(f"refined domain error inside the polygon ({kind}) at {where}, offset {off}")
         xy = base.copy()
         xy[i] = (np.float32(0.5 + off), np.float32(0.5))
         with pytest.raises(ch.DomainError):
@@ -173,9 +175,11 @@ def test_fused_path_counts(ctx):
     info = ctx.last_hull_info()
     assert info["n"] == ring.shape[0] and 0 < info["candidates"] < ring.shape[0] // 10
     assert info["survivors"] <= info["candidates"]
+    assert info["single_read"] & 1
     small = workloads.annulus(SAMPLE_MIN - 1, 94, 0.49, 0.5)
     assert np.array_equal(ctx.hull(_dev(small)), oracle.hull(small))
     assert ctx.last_hull_info()["candidates"] == 0
+    assert ctx.last_hull_info()["single_read"] == 0
     line = _cases(SAMPLE_MIN)["collinear"]
     assert np.array_equal(ctx.hull(_dev(line)), oracle.hull(line))
     assert ctx.last_hull_info()["candidates"] == 0
