@@ -703,38 +703,43 @@ __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
     return;
   }
-  // Each round a workgroup tests kR records per thread and reserves room for
+  // Each round a workgroup tests KR records per thread and reserves room for
   // all its survivors with one atomic (a counter shared by the whole grid
-  // serialises, so reservations are kept few).
-  constexpr uint32_t kR = 8;
-  constexpr uint32_t kChunk = kBlock * kR;
+  // serialises, so reservations are kept few: many candidates take 16 per
+  // thread, few take 4 and spread over more workgroups).
   __shared__ uint32_t s_base;
   const uint32_t m = *cand_count;
-  for (uint32_t s0 = blockIdx.x * kChunk; s0 < m; s0 += gridDim.x * kChunk) {
-    Rec r[kR];
-    uint32_t km = 0, cnt = 0;
+  auto rounds = [&](auto kr_tag) {
+    constexpr uint32_t KR = decltype(kr_tag)::value;
+    constexpr uint32_t kChunk = kBlock * KR;
+    for (uint32_t s0 = blockIdx.x * kChunk; s0 < m; s0 += gridDim.x * kChunk) {
+      Rec r[KR];
+      uint32_t km = 0, cnt = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < kR; ++j) {
-      const uint32_t i = s0 + j * kBlock + threadIdx.x;
-      if (i < m) {
-        r[j] = cand[i];
-        if (classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF), r[j].i,
-                            o, hdr->vidx).keep) {
-          km |= 1u << j;
-          ++cnt;
+      for (uint32_t j = 0; j < KR; ++j) {
+        const uint32_t i = s0 + j * kBlock + threadIdx.x;
+        if (i < m) {
+          r[j] = cand[i];
+          if (classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF),
+                              r[j].i, o, hdr->vidx).keep) {
+            km |= 1u << j;
+            ++cnt;
+          }
         }
       }
-    }
-    uint32_t total;
-    const uint32_t off = block_excl_scan(cnt, total);
-    if (threadIdx.x == 0 && total) s_base = atomicAdd(count_out, total);
-    __syncthreads();
-    uint32_t q = s_base + off;
+      uint32_t total;
+      const uint32_t off = block_excl_scan(cnt, total);
+      if (threadIdx.x == 0 && total) s_base = atomicAdd(count_out, total);
+      __syncthreads();
+      uint32_t q = s_base + off;
 #pragma unroll
-    for (uint32_t j = 0; j < kR; ++j)
-      if (km & (1u << j)) surv[q++] = r[j];
-    __syncthreads();  // s_base is rewritten next round
-  }
+      for (uint32_t j = 0; j < KR; ++j)
+        if (km & (1u << j)) surv[q++] = r[j];
+      __syncthreads();  // s_base is rewritten next round
+    }
+  };
+  if (m >= (1u << 18)) rounds(IntC<16>{});
+  else rounds(IntC<4>{});
 }
 
 // Pass 2 of the hull path when there is no fused pass (fewer than kSampleMin
