@@ -565,8 +565,11 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   info.survivors = hres->cin;
   bool large = false;
   int round = 0;
-  int last_list = -1;  // record list holding the latest round's output
-  while (hres->status != RES_DONE) {
+  int last_list = -1;  // record list holding the latest round's output (-1: the survivors)
+  // Many survivors (points near a smooth boundary keep about half of every
+  // tile hull): straight to the large-hull path.
+  if (hres->status == RES_MORE && hres->cin > kLargeDirect) large = true;
+  while (!large && hres->status != RES_DONE) {
     if (hres->status != RES_MORE) return fail(ctx, CH_E_DEVICE, "hull status %u", hres->status);
     const uint32_t cin = hres->cin;
     uint32_t grid = (cin + kHullTile - 1) / kHullTile;
@@ -600,7 +603,10 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   }
 
   if (large) {
-    const uint32_t cin = hres->round_cnt[round];  // output of the last round
+    // input: the last round's output, or the survivors when no round ran
+    const uint32_t cin = round ? hres->round_cnt[round] : hres->cin;
+    const Rec* lin = round ? rec[last_list] : srec;
+    const uint32_t* lcnt = round ? &res->round_cnt[round] : &hdr->count;
     Rec* lstA = at<Rec>(d_ws, L.lstA);
     Rec* lstB = at<Rec>(d_ws, L.lstB);
     const size_t chain_cap = size_t(kColumns) + 2;
@@ -610,7 +616,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     const size_t wstride = chain_cap / 4096 + 4;
     {
       ProfScope p(ctx, st, "col_build");
-      e = launch_col_build(rec[last_list], &res->round_cnt[round], cin, at<uint64_t>(d_ws, L.colbot),
+      e = launch_col_build(lin, lcnt, cin, at<uint64_t>(d_ws, L.colbot),
                            at<uint64_t>(d_ws, L.coltop), at<uint32_t>(d_ws, L.colcnt), Alo, Aup,
                            &hdr->oct, res, st);
     }

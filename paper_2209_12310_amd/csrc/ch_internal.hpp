@@ -20,6 +20,7 @@ constexpr int kHullTile = 2048;        // items per tile hull (LDS resident)
 constexpr int kFinalTile = 4096;       // items the single-workgroup final hull takes
 constexpr int kHullGridMax = 1024;
 constexpr int kMaxRounds = 48;
+constexpr uint32_t kLargeDirect = 1u << 18;  // survivors above which ch_hull skips the tile rounds
 constexpr uint32_t kHullCapMax = 1u << 21;  // strict vertices of a hull on the grid
 
 // Column table for large hulls: one bottom and one top entry per grid column.

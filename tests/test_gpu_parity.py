@@ -203,6 +203,20 @@ def test_dense_annulus_large_hull(ctx, n):
     _check_filter(ctx, xy)
 
 
+def test_many_survivors_go_straight_to_large_path(ctx):
+    """A ring ten grid units wide, every point twice (the copy at the larger
+    index first): most points survive every filter, so the hull pass skips
+    the tile rounds and runs the column table on the survivors directly;
+    copies still report their smallest index."""
+    _say("ring with duplicates, direct large path")
+    ring = workloads.annulus(1_000_000, 44, 0.49999, 0.5)
+    xy = np.concatenate([ring[::-1], ring])
+    _check_hull(ctx, xy)
+    info = ctx.last_hull_info()
+    assert info["survivors"] > (1 << 18), info
+    assert info["large_path"] == 1 and info["rounds"] == 0, info
+
+
 # --------------------------------------------------- workload configurations
 
 @pytest.mark.parametrize("name", list(workloads.SINGLE))
