@@ -788,18 +788,21 @@ __global__ __launch_bounds__(kBlock) void k_col_emit(const uint64_t* __restrict_
     if (threadIdx.x == 0) { cnt[2 * blockIdx.x] = tlo; cnt[2 * blockIdx.x + 1] = tup; }
     return;
   }
-  __shared__ uint32_t s_base[2];
-  if (threadIdx.x < 2) {
-    uint32_t s = 0;
-    for (uint32_t b = 0; b < blockIdx.x; ++b) s += cnt[2 * b + threadIdx.x];
-    s_base[threadIdx.x] = s;
-    if (blockIdx.x == gridDim.x - 1) {
-      if (threadIdx.x == 0) res->lcount = s + tlo; else res->ucount = s + tup;
-    }
+  // Counts of the earlier chunks, summed by the whole workgroup.
+  uint32_t plo = 0, pup = 0;
+  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) {
+    plo += cnt[2 * b];
+    pup += cnt[2 * b + 1];
   }
-  __syncthreads();
-  olo += s_base[0];
-  oup += s_base[1];
+  uint32_t blo, bup;
+  block_excl_scan(plo, blo);
+  block_excl_scan(pup, bup);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    res->lcount = blo + tlo;
+    res->ucount = bup + tup;
+  }
+  olo += blo;
+  oup += bup;
   for (uint32_t e = 0; e < PER; ++e) {
     const uint32_t x = x0 + e;
     const uint64_t b = bot[x];
