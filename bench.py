@@ -115,6 +115,28 @@ def cpu_baseline(xy, budget_s: float = 8.0):
             "single_thread_sample": f"{reps1} run(s) in {total1:.1f} s of the sequential heaphull"}
 
 
+def measure_read_stream(ctx, buf, reps: int = 10) -> dict:
+    """The read bandwidth this device reaches on a plain non-temporal stream
+    over the same buffer (ch_diag_read_stream), best over a few grid sizes:
+    the reference for the roofline fraction beside the vendor peak."""
+    import torch
+    by = {}
+    nbytes = 0
+    for blocks in (256, 512, 1024):
+        for _ in range(2):
+            nbytes = ctx.read_stream_async(buf, blocks)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            ctx.read_stream_async(buf, blocks)
+        b.record()
+        torch.cuda.synchronize()
+        by[blocks] = round(nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9, 1)
+    best = max(by, key=by.get)
+    return {"gbs": by[best], "blocks": best, "bytes": nbytes, "by_blocks": by,
+            "kernel": "ch_diag_read_stream: 16-byte non-temporal loads, 4 per thread per step"}
+
+
 def bench_single(ctx, name: str, steps: int, warmup: int) -> dict:
     """ch_hull end to end on one more single-set configuration."""
     import torch
@@ -359,12 +381,17 @@ def main() -> int:
     log(f"timed {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
-        hull = ctx.hull(t)
+        hull = ctx.hull(t)  # synchronous: returns with the hull in host memory
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = elapsed / args.steps * 1e3
     value = n / (ms * 1e-3) / 1e6
+    step_ms = np.diff(np.array([t0] + marks)) * 1e3
+    step_stats = {"mean": round(float(step_ms.mean()), 4), "median": round(float(np.median(step_ms)), 4),
+                  "p99": round(float(np.percentile(step_ms, 99)), 4), "min": round(float(step_ms.min()), 4)}
 
     # Kernel durations: a second region of the same steps with the library's
     # HIP events recorded on the launch stream around every kernel (they add
@@ -381,6 +408,7 @@ def main() -> int:
     info = ctx.last_hull_info()
     kernels = {k: {"launches": v[0], "mean_us": round(v[1] / max(v[0], 1) * 1e3, 2)}
                for k, v in stats.items() if v[0]}
+    read_stream = measure_read_stream(ctx, t)
     dom = max((k for k in BYTES_PER_POINT if k in stats), key=lambda k: stats[k][1])
     launches, total_ms = stats[dom]
     mean_s = total_ms / launches * 1e-3
@@ -395,7 +423,8 @@ def main() -> int:
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
-                "mean_us": round(mean_s * 1e6, 2)}
+                "mean_us": round(mean_s * 1e6, 2),
+                "frac_of_read_stream": round(achieved / read_stream["gbs"], 4)}
     sb = stage_bytes(n, info)
     filt_ms = sum(stats[k][1] / stats[k][0] for k in STAGE_KERNELS if k in stats and stats[k][0])
     filter_stage = {"bytes_per_point": sb["per_point"], "bytes": sb, "mean_us": round(filt_ms * 1e3, 2),
@@ -412,6 +441,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "step_ms": step_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -425,6 +455,7 @@ def main() -> int:
         "hull_info": info,
         "filter_stage": filter_stage,
         "roofline": roofline,
+        "read_stream": read_stream,
         "kernels": kernels,
     }
     del t

@@ -305,6 +305,16 @@ ch_status ch_profile_enable(ch_ctx* ctx, int on);
 ch_status ch_profile_reset(ch_ctx* ctx);
 ch_status ch_profile_read(ch_ctx* ctx, ch_kernel_stat* out, int cap, int* n_out);
 
+/* Diagnostic, not part of the method: reads the first `bytes` (a multiple of
+ * 16) of the device buffer d_buf once, as a plain non-temporal stream of
+ * 16-byte loads on `blocks` workgroups (0: two per CU), and returns without
+ * waiting (enqueued on `stream`). Timing it gives the read bandwidth the
+ * device reaches, the reference for the hull path's roofline fraction.
+ * d_buf must be 16-byte aligned and caller-owned. Errors: CH_E_INVALID_ARG
+ * (null context or buffer, bytes not a multiple of 16), CH_E_DEVICE. */
+ch_status ch_diag_read_stream(ch_ctx* ctx, const void* d_buf, size_t bytes, uint32_t blocks,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -166,6 +166,16 @@ class Context:
             self._raise(st)
         return out[: h.value].copy()
 
+    def read_stream_async(self, buf, blocks: int = 0):
+        """ch_diag_read_stream over a contiguous device tensor (its bytes,
+        rounded down to a multiple of 16), on the current stream."""
+        nbytes = (buf.numel() * buf.element_size()) & ~15
+        st = self._lib.ch_diag_read_stream(self._h, ctypes.c_void_p(buf.data_ptr()), nbytes, blocks,
+                                           self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+        return nbytes
+
     def last_hull_info(self) -> dict:
         """Counts of the last successful hull() on this context."""
         info = _capi.HullInfo()

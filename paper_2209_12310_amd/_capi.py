@@ -74,6 +74,7 @@ SIGNATURES = {
     "ch_hull_workspace_bytes": (SZ, [U32]),
     "ch_filter": (I32, [P, P, U32, P, P, P, P, P, SZ, P]),
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
+    "ch_diag_read_stream": (I32, [P, P, SZ, U32, P]),
     "ch_last_hull_info": (I32, [P, ctypes.POINTER(HullInfo)]),
     "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),
     "ch_hull_batch": (I32, [P, P, P, U32, U64, P, P, P, SZ, P]),

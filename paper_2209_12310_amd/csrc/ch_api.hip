@@ -53,6 +53,8 @@ hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl
                                hipStream_t st);
 hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
                               Result* res, uint32_t* res_idx, hipStream_t st);
+hipError_t launch_read_stream(const void* d_buf, size_t bytes, uint32_t blocks, float* sink,
+                              hipStream_t st);
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
@@ -809,6 +811,23 @@ ch_status ch_profile_enable(ch_ctx* ctx, int on) {
 ch_status ch_profile_reset(ch_ctx* ctx) {
   if (!ctx) return CH_E_INVALID_ARG;
   for (auto& s : ctx->stats) { s.launches = 0; s.ms = 0.0; }
+  return CH_OK;
+}
+
+ch_status ch_diag_read_stream(ch_ctx* ctx, const void* d_buf, size_t bytes, uint32_t blocks,
+                              void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (!d_buf) return fail(ctx, CH_E_INVALID_ARG, "d_buf is NULL");
+  if ((bytes & 15u) || (reinterpret_cast<uintptr_t>(d_buf) & 15u))
+    return fail(ctx, CH_E_INVALID_ARG, "bytes and d_buf must be multiples of 16");
+  if (blocks == 0) blocks = (uint32_t)ctx->cu_count * 2;
+  if (blocks > 65535) return fail(ctx, CH_E_INVALID_ARG, "blocks above 65535");
+  if (bytes == 0) return CH_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  const hipError_t e =
+      launch_read_stream(d_buf, bytes, blocks, nullptr, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "read stream launch");
   return CH_OK;
 }
 

@@ -61,6 +61,14 @@ def test_null_context_is_rejected(lib):
     assert lib.ch_filter(None, None, 0, None, None, None, None, None, 0, None) == 1
 
 
+def test_read_stream_rejects_bad_arguments(lib):
+    """The diagnostic read stream refuses a null context before touching a
+    device (its other checks need a context, see the GPU tests)."""
+    fn = lib.ch_diag_read_stream
+    fn.restype, fn.argtypes = _capi.SIGNATURES["ch_diag_read_stream"]
+    assert fn(None, None, 16, 0, None) == _capi.CH_E_INVALID_ARG
+
+
 def test_product_never_touches_the_oracle():
     pkg = os.path.join(ROOT, "paper_2209_12310_amd")
     for dirpath, _, files in os.walk(pkg):

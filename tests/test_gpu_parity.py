@@ -217,6 +217,22 @@ def test_many_survivors_go_straight_to_large_path(ctx):
     assert info["large_path"] == 1 and info["rounds"] == 0, info
 
 
+def test_read_stream_diagnostic(ctx):
+    """The diagnostic read stream runs on a device buffer and rejects a
+    length that is not a multiple of 16 bytes."""
+    import ctypes
+    import torch
+    from paper_2209_12310_amd import _capi
+    _say("read stream diagnostic")
+    buf = torch.zeros(1 << 20, dtype=torch.float32, device="cuda:0")
+    assert ctx.read_stream_async(buf) == 4 << 20
+    assert ctx.read_stream_async(buf, 7) == 4 << 20
+    torch.cuda.synchronize()
+    st = ctx._lib.ch_diag_read_stream(ctx._h, ctypes.c_void_p(buf.data_ptr()), 24, 0,
+                                      ctx.stream_handle())
+    assert st == _capi.CH_E_INVALID_ARG
+
+
 # --------------------------------------------------- workload configurations
 
 @pytest.mark.parametrize("name", list(workloads.SINGLE))
