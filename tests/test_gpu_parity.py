@@ -217,6 +217,39 @@ def test_many_survivors_go_straight_to_large_path(ctx):
     assert info["large_path"] == 1 and info["rounds"] == 0, info
 
 
+def test_max_points(ctx):
+    """CH_MAX_POINTS = 2^31 - 1 points (17 GB of input, ~112 GB of workspace):
+    uniform interior points strictly inside the grid square, its four corners
+    at the largest indices (the last one the odd tail point), and a second
+    copy of one corner at index 5. The hull is known by construction: the
+    corners, counter-clockwise from the lexicographic minimum, the duplicated
+    one reported by its smaller index."""
+    import torch
+    from paper_2209_12310_amd import _capi
+    n = _capi.CH_MAX_POINTS
+    _say(f"max points n={n}: generating on the device")
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(47)
+    k = torch.randint(1, (1 << 20) - 1, (n, 2), dtype=torch.int32, device="cuda:0", generator=g)
+    top = (1 << 20) - 1
+    corners = torch.tensor([[0, 0], [0, 0], [top, 0], [top, top], [0, top]], dtype=torch.int32,
+                           device="cuda:0")
+    k[5] = corners[0]
+    k[n - 4:] = corners[1:]
+    xy = k.to(torch.float32).mul_(2.0 ** -20)
+    del k
+    torch.cuda.synchronize()
+    _say("max points: hull")
+    got = ctx.hull(xy)
+    assert got.tolist() == [5, n - 3, n - 2, n - 1]
+    info = ctx.last_hull_info()
+    assert info["n"] == n and info["h"] == 4
+    del xy
+    ctx._ws = None
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def test_read_stream_diagnostic(ctx):
     """The diagnostic read stream runs on a device buffer and rejects a
     length that is not a multiple of 16 bytes."""
