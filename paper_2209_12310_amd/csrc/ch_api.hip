@@ -86,7 +86,7 @@ struct ch_ctx {
   int cu_count = 0;
   uint32_t reduce_max_blocks = 1024;  // persistent grid sizes, from the CU count
   uint32_t filter_max_blocks = 1024;
-  uint32_t fused_max_blocks = 768;
+  uint32_t fused_max_blocks = 512;
   uint32_t narrow_blocks = 256;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   std::string err;
@@ -423,9 +423,9 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
   if (ctx->reduce_max_blocks > (uint32_t)kReduceMaxBlocks) ctx->reduce_max_blocks = kReduceMaxBlocks;
   ctx->filter_max_blocks = (uint32_t)ctx->cu_count * 4;
   if (ctx->filter_max_blocks > (uint32_t)kFilterMaxBlocks) ctx->filter_max_blocks = kFilterMaxBlocks;
-  // The fused hull pass: three workgroups per CU when many points go to the
+  // The fused hull pass: two workgroups per CU when many points go to the
   // exact test, one per CU (fewer, longer streams) when few do.
-  ctx->fused_max_blocks = (uint32_t)ctx->cu_count * 3;
+  ctx->fused_max_blocks = (uint32_t)ctx->cu_count * 2;
   if (ctx->fused_max_blocks > (uint32_t)kReduceMaxBlocks) ctx->fused_max_blocks = kReduceMaxBlocks;
   ctx->narrow_blocks = (uint32_t)ctx->cu_count;
   // Overrides for tuning sweeps.
