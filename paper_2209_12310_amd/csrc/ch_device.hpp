@@ -22,38 +22,10 @@ __device__ __forceinline__ bool bad_turn(int32_t ax, int32_t ay, int32_t bx, int
   return LOWER ? (c <= 0.0) : (c >= 0.0);
 }
 
-// Wave-wide maximum of a 64-bit value with DPP lane moves (VALU only):
-// neighbours, quads, half rows, rows; then the four row results through
-// readlane. All 64 lanes must be active; the result is wave-uniform.
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_max_u64(uint64_t v) {
-  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, 0xF, 0xF, false);
-  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, 0xF, 0xF, false);
-  const uint64_t o = ((uint64_t)ohi << 32) | olo;
-  return o > v ? o : v;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  v = dpp_max_u64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = dpp_max_u64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v = dpp_max_u64<0x141>(v);  // row_half_mirror
-  v = dpp_max_u64<0x140>(v);  // row_mirror
-  uint64_t r = 0;
-#pragma unroll
-  for (int row = 0; row < 4; ++row) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, row * 16);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), row * 16);
-    const uint64_t x = ((uint64_t)hi << 32) | lo;
-    r = x > r ? x : r;
-  }
-  return r;
-}
+__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
 // Orders this wave's LDS accesses before and after the call (the waves of a
 // workgroup are not synchronised).
-__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -281,57 +281,114 @@ struct WinSmem {
 template <int T>
 constexpr int maxc() { return (T / kBlock + 1) / 2; }
 
-// ------------------------------------------------ small inputs: one wave per chain
+// A 64-bit lane move through DPP (all 64 lanes active).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)v, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(v >> 32), (int)(uint32_t)(v >> 32), CTRL,
+                                                            0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One halving step of wave_max16_t: partners (the DPP pattern CTRL) differ in
+// lane bit B and hold the same 2H values; the lane with bit B set keeps the
+// upper H, its partner the lower H, and each takes the maximum with the half
+// the other sends.
+template <int CTRL, int B, int H>
+__device__ __forceinline__ void max_half(const uint64_t (&in)[2 * H], uint64_t (&out)[H], int lane) {
+  const bool up = (lane >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const uint64_t keep = up ? in[j + H] : in[j];
+    const uint64_t send = up ? in[j] : in[j + H];
+    const uint64_t got = dpp_u64<CTRL>(send);
+    out[j] = got > keep ? got : keep;
+  }
+}
+
+// Wave-wide maxima of 16 values per lane, transposed: lane l returns the
+// maximum of value l mod 16 over all 64 lanes. Row mirror (bit 3), half-row
+// mirror (bit 2) and the two quad swaps (bits 1, 0) pair lanes that hold the
+// same values at each step, so one row ends with one value per lane; two
+// cross-row exchanges finish. All 64 lanes must be active.
+__device__ __forceinline__ uint64_t wave_max16_t(const uint64_t (&b)[16], int lane) {
+  uint64_t c8[8], c4[4], c2[2], c1[1];
+  max_half<0x140, 3, 8>(b, c8, lane);   // row_mirror
+  max_half<0x141, 2, 4>(c8, c4, lane);  // row_half_mirror
+  max_half<0x4E, 1, 2>(c4, c2, lane);   // quad_perm [2,3,0,1]
+  max_half<0xB1, 0, 1>(c2, c1, lane);   // quad_perm [1,0,3,2]
+  uint64_t v = c1[0];
+  uint64_t o = __shfl_xor(v, 16);
+  v = o > v ? o : v;
+  o = __shfl_xor(v, 32);
+  return o > v ? o : v;
+}
+
+// ------------------------------------------------ small inputs: two waves per chain
 //
 // When the pre-filter leaves few candidates (at most kSmallChain per chain),
-// each chain is built by one wave with no workgroup barrier inside: a
-// register bitonic sort, duplicate removal, and a parallel vertex test. For
-// points p_0 < ... < p_(m-1) in (x, y) order, p_i is a strict lower-chain
-// vertex exactly when orient(p_j, p_i, p_k) > 0 for every j < i < k, i.e.
-// for the j whose direction p_j -> p_i turns furthest counter-clockwise and
-// the k whose direction p_i -> p_k turns furthest clockwise (both sets of
-// directions lie within a half-turn, so these are well defined); the upper
-// chain mirrors the signs. Each lane finds the two extreme neighbours of its
-// points in one pass over the chain, then tests those triples. Item e of
-// lane l is element 64 e + l.
+// each chain is built without a sort. For distinct points in (x, y) order, p
+// is a strict lower-chain vertex exactly when orient(a, p, b) > 0 for every a
+// before p and every b after it: when every slope a -> p is below every slope
+// p -> b (a point straight above or below counts as slope +infinity in the
+// direction of increasing order); the upper chain mirrors the signs. Each
+// point's largest slope to the left and smallest to the right come from one
+// pass over the chain. The slopes are quotients of integers below 2^21, so
+// two different ones differ by at least 2^-42 of their size, far above an
+// fp64 rounding: correctly rounded fp64 quotients keep every strict order and
+// every equality, and the comparison of the two bounds is exact. Two waves
+// share a chain (each takes half the pairs); equal points keep the smallest
+// index; the vertices are placed by rank.
 constexpr uint32_t kSmallChain = 128;
 
-// Ascending sort of 128 64-bit keys, two per lane.
-__device__ __forceinline__ void wave_sort128(uint64_t& v0, uint64_t& v1, int lane) {
+// Points per lane of a chain scan (1 or 2), as a compile-time tag.
+template <int N>
+struct Slots {
+  static constexpr int value = N;
+};
+
+// Lexicographic minimum and maximum of a 64-bit key over the wave (DPP row
+// steps, then two cross-row exchanges). All 64 lanes must be active.
+__device__ __forceinline__ void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
+  auto step = [&](auto ctrl_tag) {
+    constexpr int C = decltype(ctrl_tag)::value;
+    const uint64_t a = dpp_u64<C>(mn), b = dpp_u64<C>(mx);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  };
+  step(Slots<0xB1>{});   // quad_perm [1,0,3,2]
+  step(Slots<0x4E>{});   // quad_perm [2,3,0,1]
+  step(Slots<0x141>{});  // row_half_mirror
+  step(Slots<0x140>{});  // row_mirror
 #pragma unroll
-  for (int k = 2; k <= 128; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j == 64) {  // k == 128: the pair of one lane, ascending
-        const uint64_t lo = v0 < v1 ? v0 : v1, hi = v0 < v1 ? v1 : v0;
-        v0 = lo;
-        v1 = hi;
-      } else {
-        const uint64_t o0 = __shfl_xor(v0, j), o1 = __shfl_xor(v1, j);
-        const bool low = (lane & j) == 0;
-        const bool asc0 = (lane & k) == 0, asc1 = ((lane + 64) & k) == 0;
-        v0 = (asc0 == low) ? (o0 < v0 ? o0 : v0) : (o0 > v0 ? o0 : v0);
-        v1 = (asc1 == low) ? (o1 < v1 ? o1 : v1) : (o1 > v1 ? o1 : v1);
-      }
-    }
+  for (int o = 16; o <= 32; o <<= 1) {
+    const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
   }
 }
 
 // Whole workgroup. The `kept` (1..2 kSmallChain) candidates are in sm.a.key
-// (x<<44 | y<<24 | position) with their indices in sm.b.pidx. Wave 0 builds
-// the lower chain into px/py/pi, wave 1 the upper chain into a.u / b.ui
-// (both from the lexicographic minimum to the maximum, ends included).
-// Returns false, with sm untouched, when a chain has more than kSmallChain
-// candidates.
+// (x<<44 | y<<24 | position) with their indices in sm.b.pidx. The lower chain
+// goes to px/py/pi, the upper chain to a.u / b.ui (both from the
+// lexicographic minimum to the maximum, ends included). Waves 0-1 take the
+// lower chain, waves 2-3 the upper one. Returns false, with sm untouched,
+// when a chain has more than kSmallChain candidates.
 template <int T>
 __device__ bool small_chains(HullSmem<T>& sm, uint32_t kept, uint32_t& nl, uint32_t& nu) {
-  __shared__ uint32_t s_n[2];
-  __shared__ uint64_t s_key[2][kSmallChain];
-  __shared__ uint32_t s_id[2][kSmallChain];
+  static_assert(kWaves == 4, "two waves per chain");
+  __shared__ uint32_t s_n[2], s_vc[2][2];
   __shared__ int32_t s_x[2][kSmallChain], s_y[2][kSmallChain];
   __shared__ uint32_t s_ui[2][kSmallChain];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ uint64_t s_vt[2][kSmallChain];  // chain vertices (x<<20 | y)
+  __shared__ double s_pl[2][64], s_pr[2][64];  // second half's bounds (chains of <= 64)
+  __shared__ uint32_t s_pf[2][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t lt = (1ull << lane) - 1ull;
+  // Waves 0 and 1 select the candidates of the lower / upper chain: the ends
+  // (lexicographic minimum and maximum) and the points strictly below /
+  // above the line through them.
   uint64_t sel[4] = {0, 0, 0, 0};
   uint64_t kin[4];
   if (w < 2) {
@@ -344,13 +401,7 @@ __device__ bool small_chains(HullSmem<T>& sm, uint32_t kept, uint32_t& nl, uint3
       mn = kin[e] < mn ? kin[e] : mn;
       mx = v[e] && kin[e] > mx ? kin[e] : mx;
     }
-    // lexicographic minimum and maximum (keys order by x, then y)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
-      mn = a < mn ? a : mn;
-      mx = b > mx ? b : mx;
-    }
+    wave_minmax_u64(mn, mx);
     const int32_t ax = (int32_t)(mn >> 44), ay = (int32_t)((mn >> 24) & 0xFFFFFu);
     const int32_t bx = (int32_t)(mx >> 44), by = (int32_t)((mx >> 24) & 0xFFFFFu);
     uint32_t c = 0;
@@ -369,110 +420,108 @@ __device__ bool small_chains(HullSmem<T>& sm, uint32_t kept, uint32_t& nl, uint3
   }
   __syncthreads();
   if (s_n[0] > kSmallChain || s_n[1] > kSmallChain) return false;
-  int32_t ox[2] = {0, 0}, oy[2] = {0, 0};
-  uint32_t oi[2] = {0, 0};
-  bool vert[2] = {false, false};
-  if (w < 2) {
-    // compact the chain's candidates, sort them, drop repeats (each
-    // distinct point keeps its smallest index)
-    const uint32_t c = s_n[w];
+  if (w < 2) {  // compact the chain's candidates (unordered)
     uint32_t base = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if ((sel[e] >> lane) & 1ull) s_key[w][base + popc64(sel[e] & lt)] = kin[e];
+      if ((sel[e] >> lane) & 1ull) {
+        const uint32_t pos = base + popc64(sel[e] & lt);
+        s_x[w][pos] = (int32_t)(kin[e] >> 44);
+        s_y[w][pos] = (int32_t)((kin[e] >> 24) & 0xFFFFFu);
+        s_ui[w][pos] = sm.b.pidx[kin[e] & 0xFFFFFFu];
+      }
       base += popc64(sel[e]);
     }
-    __builtin_amdgcn_wave_barrier();
-    uint64_t v0 = (uint32_t)lane < c ? s_key[w][lane] : ~0ull;
-    uint64_t v1 = (uint32_t)lane + 64 < c ? s_key[w][lane + 64] : ~0ull;
-    wave_sort128(v0, v1, lane);
-    __builtin_amdgcn_wave_barrier();
-    s_key[w][lane] = v0;
-    s_key[w][lane + 64] = v1;
-    s_id[w][lane] = (uint32_t)lane < c ? sm.b.pidx[v0 & 0xFFFFFFu] : 0u;
-    s_id[w][lane + 64] = (uint32_t)lane + 64 < c ? sm.b.pidx[v1 & 0xFFFFFFu] : 0u;
-    __builtin_amdgcn_wave_barrier();
-    uint64_t fm[2];
-    uint64_t upt[2];
-    uint32_t umi[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const uint32_t i = (uint32_t)lane + 64 * e;
-      const uint64_t pt = s_key[w][i] >> 24;
-      const bool first = i < c && (i == 0 || (s_key[w][i - 1] >> 24) != pt);
-      uint32_t mi = s_id[w][i];
-      if (first)
-        for (uint32_t q = i + 1; q < c && (s_key[w][q] >> 24) == pt; ++q) mi = s_id[w][q] < mi ? s_id[w][q] : mi;
-      fm[e] = __builtin_amdgcn_ballot_w64(first);
-      upt[e] = pt;
-      umi[e] = mi;
-    }
-    const uint32_t m = popc64(fm[0]) + popc64(fm[1]);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      if ((fm[e] >> lane) & 1ull) {
-        const uint32_t pos = (e ? popc64(fm[0]) : 0u) + popc64(fm[e] & lt);
-        s_x[w][pos] = (int32_t)(upt[e] >> 20);
-        s_y[w][pos] = (int32_t)(upt[e] & 0xFFFFFu);
-        s_ui[w][pos] = umi[e];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    // sg = +1 for the lower chain, -1 for the upper one (mirrored signs)
-    const double sg = w == 0 ? 1.0 : -1.0;
-    const uint32_t i0 = (uint32_t)lane, i1 = (uint32_t)lane + 64;
-    const int32_t x0 = i0 < m ? s_x[w][i0] : 0, y0 = i0 < m ? s_y[w][i0] : 0;
-    const int32_t x1 = i1 < m ? s_x[w][i1] : 0, y1 = i1 < m ? s_y[w][i1] : 0;
-    int32_t jx0 = 0, jy0 = 0, kx0 = 0, ky0 = 0, jx1 = 0, jy1 = 0, kx1 = 0, ky1 = 0;
-    bool hj0 = false, hk0 = false, hj1 = false, hk1 = false;
-#pragma unroll 4
-    for (uint32_t q = 0; q < m; ++q) {
-      const int32_t qx = s_x[w][q], qy = s_y[w][q];  // one address: an LDS broadcast
-      // left of i: keep the direction q -> i furthest counter-clockwise
-      // (lower) / clockwise (upper); right of i: the direction i -> q
-      // furthest clockwise (lower) / counter-clockwise (upper)
-      {
-        const double o = sg * cross3(x0, y0, q < i0 ? jx0 : kx0, q < i0 ? jy0 : ky0, qx, qy);
-        if (q < i0 && (!hj0 || o > 0.0)) { jx0 = qx; jy0 = qy; hj0 = true; }
-        if (q > i0 && (!hk0 || o < 0.0)) { kx0 = qx; ky0 = qy; hk0 = true; }
-      }
-      {
-        const double o = sg * cross3(x1, y1, q < i1 ? jx1 : kx1, q < i1 ? jy1 : ky1, qx, qy);
-        if (q < i1 && (!hj1 || o > 0.0)) { jx1 = qx; jy1 = qy; hj1 = true; }
-        if (q > i1 && (!hk1 || o < 0.0)) { kx1 = qx; ky1 = qy; hk1 = true; }
-      }
-    }
-    // a strict vertex: the first or last point, or a strict turn of the
-    // chain's direction between the two extreme neighbours
-    vert[0] = i0 < m && (!hj0 || !hk0 || sg * cross3(jx0, jy0, x0, y0, kx0, ky0) > 0.0);
-    vert[1] = i1 < m && (!hj1 || !hk1 || sg * cross3(jx1, jy1, x1, y1, kx1, ky1) > 0.0);
-    ox[0] = x0; oy[0] = y0; oi[0] = i0 < m ? s_ui[w][i0] : 0u;
-    ox[1] = x1; oy[1] = y1; oi[1] = i1 < m ? s_ui[w][i1] : 0u;
-  }
-  __syncthreads();  // every read of a.key / b.pidx is done: the upper chain may overwrite them
-  if (w < 2) {
-    const uint64_t vm0 = __builtin_amdgcn_ballot_w64(vert[0]), vm1 = __builtin_amdgcn_ballot_w64(vert[1]);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      if (vert[e]) {
-        const uint32_t pos = (e ? popc64(vm0) : 0u) + popc64((e ? vm1 : vm0) & lt);
-        if (w == 0) { sm.px[pos] = ox[e]; sm.py[pos] = oy[e]; sm.pi[pos] = oi[e]; }
-        else { sm.a.u.ux[pos] = ox[e]; sm.a.u.uy[pos] = oy[e]; sm.b.ui[pos] = oi[e]; }
-      }
-    }
-    if (lane == 0) s_n[w] = popc64(vm0) + popc64(vm1);
   }
   __syncthreads();
-  nl = s_n[0];
-  nu = s_n[1];
+  // Chain ch = w / 2, half hf = w % 2. Up to 64 points: both halves take
+  // point `lane`, each over half of the chain; more: half hf takes point
+  // lane + 64 hf over the whole chain.
+  const int ch = w >> 1, hf = w & 1;
+  const uint32_t c = __builtin_amdgcn_readfirstlane(s_n[ch]);
+  const bool split = c <= 64;
+  const uint32_t i = split ? (uint32_t)lane : (uint32_t)lane + 64 * hf;
+  const uint32_t q0 = split && hf ? (c + 1) / 2 : 0;
+  const uint32_t q1 = split && !hf ? (c + 1) / 2 : c;
+  const bool has = i < c;
+  const int32_t px = has ? s_x[ch][i] : 0, py = has ? s_y[ch][i] : 0;
+  const uint32_t pid = has ? s_ui[ch][i] : 0u;
+  double lmax = -__builtin_inf(), rmin = __builtin_inf();
+  bool dup = false, hl = false, hr = false;
+  auto scan = [&](auto up_tag) {
+    constexpr bool UP = decltype(up_tag)::value == 1;  // mirrored slopes for the upper chain
+#pragma unroll 4
+    for (uint32_t q = q0; q < q1; ++q) {
+      const int32_t qx = s_x[ch][q], qy = s_y[ch][q];  // one address: an LDS broadcast
+      const uint32_t qi = s_ui[ch][q];
+      const bool same = (qx == px) & (qy == py);
+      const bool left = (qx < px) | ((qx == px) & (qy < py));
+      const bool right = !left & !same;
+      const int32_t dx = left ? px - qx : qx - px;
+      const int32_t dy = left ? py - qy : qy - py;
+      const double t = (double)(UP ? -dy : dy) / (double)dx;
+      dup |= same & (qi < pid);
+      lmax = left && t > lmax ? t : lmax;
+      rmin = right && t < rmin ? t : rmin;
+      hl |= left;
+      hr |= right;
+    }
+  };
+  if (ch == 0) scan(Slots<0>{});
+  else scan(Slots<1>{});
+  if (split && hf) {
+    s_pl[ch][lane] = lmax;
+    s_pr[ch][lane] = rmin;
+    s_pf[ch][lane] = (dup ? 1u : 0u) | (hl ? 2u : 0u) | (hr ? 4u : 0u);
+  }
+  __syncthreads();
+  bool vert = false;
+  if (!(split && hf)) {
+    if (split) {
+      const double l2 = s_pl[ch][lane], r2 = s_pr[ch][lane];
+      const uint32_t f2 = s_pf[ch][lane];
+      lmax = l2 > lmax ? l2 : lmax;
+      rmin = r2 < rmin ? r2 : rmin;
+      dup |= (f2 & 1u) != 0;
+      hl |= (f2 & 2u) != 0;
+      hr |= (f2 & 4u) != 0;
+    }
+    vert = has && !dup && (!hl || !hr || lmax < rmin);
+  }
+  // place the vertices by rank in (x, y) order
+  const uint64_t vm = __builtin_amdgcn_ballot_w64(vert);
+  if (lane == 0) s_vc[ch][hf] = popc64(vm);
+  __syncthreads();
+  const uint32_t n0 = s_vc[ch][0], nv = n0 + s_vc[ch][1];
+  const uint64_t key = ((uint64_t)(uint32_t)px << 20) | (uint32_t)py;
+  if (vert) s_vt[ch][(hf ? n0 : 0u) + popc64(vm & lt)] = key;
+  __syncthreads();
+  uint32_t rank = 0;
+  if (vert)
+    for (uint32_t v = 0; v < nv; ++v) rank += s_vt[ch][v] < key;
+  // every read of a.key / b.pidx is long done: the upper chain may overwrite them
+  if (vert) {
+    if (ch == 0) { sm.px[rank] = px; sm.py[rank] = py; sm.pi[rank] = pid; }
+    else { sm.a.u.ux[rank] = px; sm.a.u.uy[rank] = py; sm.b.ui[rank] = pid; }
+  }
+  __syncthreads();
+  nl = s_vc[0][0] + s_vc[0][1];
+  nu = s_vc[1][0] + s_vc[1][1];
   return true;
 }
 
 // Directions of the pre-filter polygon: 16 small-integer vectors in
 // counter-clockwise order (0, 22, 45, 68, 90, ... degrees). Dot products with
 // grid points stay below 7 * 2^20, exact in int32.
-__constant__ int8_t kDirX[16] = {1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2, 0, 2, 1, 5};
-__constant__ int8_t kDirY[16] = {0, 2, 1, 5, 1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2};
+// (Compile-time constants: the products fold into shifts and adds.)
+__device__ __forceinline__ constexpr int dir_x(int d) {
+  constexpr int8_t v[16] = {1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2, 0, 2, 1, 5};
+  return v[d];
+}
+__device__ __forceinline__ constexpr int dir_y(int d) {
+  constexpr int8_t v[16] = {0, 2, 1, 5, 1, 5, 1, 2, 0, -2, -1, -5, -1, -5, -1, -2};
+  return v[d];
+}
 
 // Hull of the `cnt` records starting at in_rec[base]. Returns h; the
 // counter-clockwise hull is element k of hull_elem().
@@ -491,10 +540,12 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
   constexpr uint32_t E = T / kBlock;  // items per thread: i = threadIdx.x + e * kBlock
   __shared__ uint64_t s_ext[kWaves][16];
   __shared__ int32_t s_vx[16], s_vy[16];
+  __shared__ double s_ex[16], s_ney[16], s_c[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (tm) CH_MARK(tm, 2);
   // Extreme position per direction: max of (dot, -position) per thread, then
-  // per wave (DPP), then over the waves.
+  // per wave (transposed DPP exchange: lane l ends with direction l mod 16),
+  // then over the waves.
   {
     uint64_t best[16];
 #pragma unroll
@@ -503,42 +554,55 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
       const int32_t x = sm.px[i], y = sm.py[i];
 #pragma unroll
       for (int d = 0; d < 16; ++d) {
-        const int32_t dot = kDirX[d] * x + kDirY[d] * y + (1 << 23);
+        const int32_t dot = dir_x(d) * x + dir_y(d) * y + (1 << 23);
         const uint64_t key = ((uint64_t)(uint32_t)dot << 32) | (0xFFFFFFFFu - i);
         best[d] = key > best[d] ? key : best[d];
       }
     }
-#pragma unroll
-    for (int d = 0; d < 16; ++d) {
-      const uint64_t m = wave_max_u64(best[d]);
-      if (lane == 0) s_ext[w][d] = m;
-    }
+    const uint64_t m = wave_max16_t(best, lane);
+    if (lane < 16) s_ext[w][lane] = m;
   }
   __syncthreads();
   if (tm) CH_MARK(tm, 9);
+  // Thread d takes vertices d and d+1 and writes side d as
+  // orient(v_d, v_(d+1), p) = ex * py + ney * px + c, exact in fp64 (each
+  // product below 2^42, each partial sum below 2^43).
   if (threadIdx.x < 16) {
-    uint64_t b = s_ext[0][threadIdx.x];
+    const int d = threadIdx.x, d2 = (d + 1) & 15;
+    uint64_t b = s_ext[0][d], b2 = s_ext[0][d2];
 #pragma unroll
-    for (int q = 1; q < kWaves; ++q) b = s_ext[q][threadIdx.x] > b ? s_ext[q][threadIdx.x] : b;
-    const uint32_t p = 0xFFFFFFFFu - (uint32_t)b;
-    s_vx[threadIdx.x] = cnt ? sm.px[p] : 0;
-    s_vy[threadIdx.x] = cnt ? sm.py[p] : 0;
+    for (int q = 1; q < kWaves; ++q) {
+      b = s_ext[q][d] > b ? s_ext[q][d] : b;
+      b2 = s_ext[q][d2] > b2 ? s_ext[q][d2] : b2;
+    }
+    const uint32_t p = 0xFFFFFFFFu - (uint32_t)b, p2 = 0xFFFFFFFFu - (uint32_t)b2;
+    const int32_t ax = cnt ? sm.px[p] : 0, ay = cnt ? sm.py[p] : 0;
+    const int32_t bx = cnt ? sm.px[p2] : 0, by = cnt ? sm.py[p2] : 0;
+    s_vx[d] = ax;
+    s_vy[d] = ay;
+    const double ex = (double)(bx - ax), ey = (double)(by - ay);
+    s_ex[d] = ex;
+    s_ney[d] = -ey;
+    s_c[d] = ey * (double)ax - ex * (double)ay;
   }
   __syncthreads();
-  // Keep a candidate outside some polygon side, or equal to a vertex.
+  // Keep a candidate outside some polygon side, or equal to a vertex (then
+  // on the boundary: no side value below zero and one equal to zero).
   uint32_t keepmask = 0, nkeep = 0;
 #pragma unroll
   for (uint32_t e = 0; e < E; ++e) {
     const uint32_t i = threadIdx.x + e * kBlock;
     if (i < cnt) {
       const int32_t x = sm.px[i], y = sm.py[i];
-      bool keep = false;
+      const double fx = (double)x, fy = (double)y;
+      double mn = __builtin_inf();
 #pragma unroll
-      for (int d = 0; d < 16; ++d) {
-        const int d2 = (d + 1) & 15;
-        const int32_t ax = s_vx[d], ay = s_vy[d], bx = s_vx[d2], by = s_vy[d2];
-        keep |= cross3(ax, ay, bx, by, x, y) < 0.0;
-        keep |= (x == ax) & (y == ay);
+      for (int d = 0; d < 16; ++d)
+        mn = __builtin_fmin(mn, __builtin_fma(s_ex[d], fy, __builtin_fma(s_ney[d], fx, s_c[d])));
+      bool keep = mn < 0.0;
+      if (mn == 0.0) {
+#pragma unroll
+        for (int d = 0; d < 16; ++d) keep |= (x == s_vx[d]) & (y == s_vy[d]);
       }
       if (keep) { keepmask |= 1u << e; ++nkeep; }
     }
