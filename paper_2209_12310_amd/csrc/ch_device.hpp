@@ -106,16 +106,25 @@ __device__ __forceinline__ bool poly_strict_inside(const int32_t* vx, const int3
   return cross3(vx[lo], vy[lo], vx[hi], vy[hi], px, py) > 0.0;
 }
 
+// Inclusive scan over the wave with DPP (VALU only): Hillis-Steele within
+// each row of 16 lanes (row shifts by 1, 2, 4, 8; lanes without a source add
+// 0), then each row adds the running total of the rows before it through the
+// row broadcasts of lanes 15 and 31. All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1, 3
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2, 3
+  return v;
+}
+
 // Block-wide exclusive scan of one value per thread (all threads call it).
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t& total) {
   __shared__ uint32_t s_w[kWaves];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t u = __shfl_up(incl, d);
-    if (lane >= d) incl += u;
-  }
+  const uint32_t incl = wave_incl_scan(v);
   if (lane == 63) s_w[w] = incl;
   __syncthreads();
   uint32_t off = 0, tot = 0;
