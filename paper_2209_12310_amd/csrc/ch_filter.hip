@@ -709,22 +709,31 @@ __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __rest
   // thread, few take 4 and spread over more workgroups).
   __shared__ uint32_t s_base;
   const uint32_t m = *cand_count;
+  if (blockIdx.x * kBlock * 4 >= m) return;  // no records for this workgroup
+  // The octagon in LDS: one global read per workgroup, not one per record.
+  __shared__ Octagon s_oct;
+  if (threadIdx.x < sizeof(Octagon) / 4)
+    reinterpret_cast<uint32_t*>(&s_oct)[threadIdx.x] = reinterpret_cast<const uint32_t*>(o)[threadIdx.x];
+  __syncthreads();
   auto rounds = [&](auto kr_tag) {
     constexpr uint32_t KR = decltype(kr_tag)::value;
     constexpr uint32_t kChunk = kBlock * KR;
     for (uint32_t s0 = blockIdx.x * kChunk; s0 < m; s0 += gridDim.x * kChunk) {
       Rec r[KR];
       uint32_t km = 0, cnt = 0;
+      // all loads first (clamped to the last record), then the tests
 #pragma unroll
       for (uint32_t j = 0; j < KR; ++j) {
         const uint32_t i = s0 + j * kBlock + threadIdx.x;
-        if (i < m) {
-          r[j] = cand[i];
-          if (classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF),
-                              r[j].i, o, hdr->vidx).keep) {
-            km |= 1u << j;
-            ++cnt;
-          }
+        r[j] = cand[i < m ? i : m - 1];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < KR; ++j) {
+        const uint32_t i = s0 + j * kBlock + threadIdx.x;
+        if (i < m && classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF),
+                                     r[j].i, &s_oct, hdr->vidx).keep) {
+          km |= 1u << j;
+          ++cnt;
         }
       }
       uint32_t total;

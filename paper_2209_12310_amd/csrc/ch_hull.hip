@@ -706,9 +706,20 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
 template <int T>
 __device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, uint32_t base,
                               uint32_t cnt, uint32_t& nl, uint32_t& nu, Result* tm = nullptr) {
-  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
-    const Rec r = in_rec[base + i];
-    sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
+  // four loads in flight per thread (clamped to the last record), then the stores
+  constexpr uint32_t kLd = 4;
+  for (uint32_t i0 = 0; i0 < cnt; i0 += kLd * kBlock) {
+    Rec r[kLd];
+#pragma unroll
+    for (uint32_t u = 0; u < kLd; ++u) {
+      const uint32_t i = i0 + u * kBlock + threadIdx.x;
+      r[u] = in_rec[base + (i < cnt ? i : cnt - 1)];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kLd; ++u) {
+      const uint32_t i = i0 + u * kBlock + threadIdx.x;
+      if (i < cnt) { sm.px[i] = r[u].x; sm.py[i] = r[u].y; sm.pi[i] = r[u].i; }
+    }
   }
   __syncthreads();
   return tile_hull_core<T>(sm, cnt, nl, nu, tm);

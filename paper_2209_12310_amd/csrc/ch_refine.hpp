@@ -351,10 +351,18 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
     uint32_t step = 1;
     while (step * 2 <= m) step *= 2;
     for (; step > 0; step >>= 1) {
+      // Loads first (clamped, unconditional), so all of them are in flight
+      // together; then the updates.
+      double v[2 * kQ];
 #pragma unroll
       for (uint32_t q = 0; q < 2 * kQ; ++q) {
         const uint32_t c = pos[q] + step;
-        if (c < m && s_t[c] <= th[q]) pos[q] = c;
+        v[q] = s_t[c < m ? c : m - 1];
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < 2 * kQ; ++q) {
+        const uint32_t c = pos[q] + step;
+        pos[q] = (c < m) & (v[q] <= th[q]) ? c : pos[q];
       }
     }
     const double t0 = s_t[0];
