@@ -106,6 +106,47 @@ __device__ __forceinline__ bool poly_strict_inside(const int32_t* vx, const int3
   return cross3(vx[lo], vy[lo], vx[hi], vy[hi], px, py) > 0.0;
 }
 
+// A 32- or 64-bit lane move through DPP (all 64 lanes active).
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_mov(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, ((uint64_t)b << 32) | a);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T read_lane(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(T, ((uint64_t)b << 32) | a);
+  }
+}
+
+// Wave-wide reduction with an associative, commutative op: neighbour and
+// quad swaps, then the half-row and row mirrors leave every lane of a row
+// with the row's result; the four rows combine through readlane. All 64
+// lanes must be active; the result is wave-uniform.
+template <class T, class Op>
+__device__ __forceinline__ T wave_allreduce(T v, Op op) {
+  v = op(v, dpp_mov<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_mov<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_mov<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_mov<0x140>(v));  // row_mirror
+  return op(op(read_lane(v, 0), read_lane(v, 16)), op(read_lane(v, 32), read_lane(v, 48)));
+}
+
 // Inclusive scan over the wave with DPP (VALU only): Hillis-Steele within
 // each row of 16 lanes (row shifts by 1, 2, 4, 8; lanes without a source add
 // 0), then each row adds the running total of the rows before it through the

@@ -89,14 +89,10 @@ __device__ __forceinline__ void keys_from_array(Keys& k, const double* a) {
 }
 
 __device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o));
-  return v;
+  return wave_allreduce(v, [](double a, double b) { return __builtin_fmax(a, b); });
 }
 __device__ __forceinline__ double wmin(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmin(v, __shfl_xor(v, o));
-  return v;
+  return wave_allreduce(v, [](double a, double b) { return __builtin_fmin(a, b); });
 }
 
 // Reduce a block's keys; the result is valid in thread 0.
@@ -162,9 +158,7 @@ __device__ double box_scale_lane(const int64_t* vx, const int64_t* vy, int lane)
     if (kk < 0) t = Lc / -kk;
     else if (Lc < 0) t = -1.0;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) t = __builtin_fmin(t, __shfl_xor(t, o));
-  return t;
+  return wmin(t);
 }
 
 // One wave: decode the octagon from the slot keys, check the domain, write
@@ -190,8 +184,8 @@ __device__ void octagon_wave(const Keys& k, Octagon& o, uint32_t* vidx, uint32_t
   int64_t vx[8], vy[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    vx[s] = __shfl(mx, s);
-    vy[s] = __shfl(my, s);
+    vx[s] = read_lane(mx, s);
+    vy[s] = read_lane(my, s);
   }
   if (lane < 8) {
     const int t = (lane + 1) & 7;
@@ -393,7 +387,7 @@ __device__ uint32_t combine_partials(const double* __restrict__ partials,
     double v[8];
     keys_to_array(k, v);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = __shfl(v[i], 0);
+    for (int i = 0; i < 8; ++i) v[i] = read_lane(v[i], 0);
     keys_from_array(k, v);
   }
   return s_bad;

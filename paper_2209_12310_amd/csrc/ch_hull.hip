@@ -347,25 +347,11 @@ struct Slots {
   static constexpr int value = N;
 };
 
-// Lexicographic minimum and maximum of a 64-bit key over the wave (DPP row
-// steps, then two cross-row exchanges). All 64 lanes must be active.
+// Lexicographic minimum and maximum of a 64-bit key over the wave
+// (wave-uniform). All 64 lanes must be active.
 __device__ __forceinline__ void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
-  auto step = [&](auto ctrl_tag) {
-    constexpr int C = decltype(ctrl_tag)::value;
-    const uint64_t a = dpp_u64<C>(mn), b = dpp_u64<C>(mx);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  };
-  step(Slots<0xB1>{});   // quad_perm [1,0,3,2]
-  step(Slots<0x4E>{});   // quad_perm [2,3,0,1]
-  step(Slots<0x141>{});  // row_half_mirror
-  step(Slots<0x140>{});  // row_mirror
-#pragma unroll
-  for (int o = 16; o <= 32; o <<= 1) {
-    const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
+  mn = wave_allreduce(mn, [](uint64_t a, uint64_t b) { return a < b ? a : b; });
+  mx = wave_allreduce(mx, [](uint64_t a, uint64_t b) { return a > b ? a : b; });
 }
 
 // Whole workgroup. The `kept` (1..2 kSmallChain) candidates are in sm.a.key

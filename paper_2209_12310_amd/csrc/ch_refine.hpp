@@ -126,8 +126,7 @@ __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_
     my[j] = (int32_t)(ax > ay ? ay : ax);
     smax = __builtin_fmin(smax, s_o[j] / (double)mx[j]);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmin(smax, __shfl_xor(smax, o));
+  smax = wave_allreduce(smax, [](double a, double b) { return __builtin_fmin(a, b); });
   if (lane == 0) s_smax[w] = smax;
   if (threadIdx.x == 0) s_fail = 0;
   __syncthreads();
@@ -236,11 +235,13 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
       sa += cr; scx += (x0 + x1) * cr; scy += (y0 + y1) * cr;
       sx += px[j]; sy += py[j];
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      sa += __shfl_xor(sa, o); scx += __shfl_xor(scx, o); scy += __shfl_xor(scy, o);
-      sx += __shfl_xor(sx, o); sy += __shfl_xor(sy, o);
-    }
+    auto add_d = [](double a, double b) { return a + b; };
+    auto add_i = [](int64_t a, int64_t b) { return a + b; };
+    sa = wave_allreduce(sa, add_d);
+    scx = wave_allreduce(scx, add_d);
+    scy = wave_allreduce(scy, add_d);
+    sx = wave_allreduce(sx, add_i);
+    sy = wave_allreduce(sy, add_i);
     bool good = false;
     int64_t cx = 0, cy = 0;
     double r2 = 0.0;
@@ -266,11 +267,8 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
         const double od = (double)o;
         r2 = __builtin_fmin(r2, od * od / (double)(ex * ex + ey * ey));
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        ups += __shfl_xor(ups, o);
-        r2 = __builtin_fmin(r2, __shfl_xor(r2, o));
-      }
+      ups = wave_allreduce(ups, [](uint32_t a, uint32_t b) { return a + b; });
+      r2 = wave_allreduce(r2, [](double a, double b) { return __builtin_fmin(a, b); });
       good = __ballot(!ok) == 0 && ups == 1;
     }
     if (lane == 0) {
