@@ -27,6 +27,7 @@ hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, ui
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
                             hipStream_t st);
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
+                              uint32_t* count0,
                               hipStream_t st);
 hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
                             uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
@@ -38,7 +39,9 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st);
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
                              const SamplePoly* gate, const Rec* cand, const void* scratch,
-                             uint32_t* ncand_out, uint32_t* mode_out, hipStream_t st);
+                             uint32_t* ncand_out, uint32_t* mode_out, const double* partials,
+                             const uint32_t* part_bad, uint32_t nparts, Result* res,
+                             hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
                              uint32_t* res_idx, const Octagon* oct, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
@@ -204,8 +207,9 @@ T* at(void* ws, size_t off) {
 // reduction, octagon build) and the ordered pass 2. Hull path (records into
 // surv_rec): below kSampleMin points, pass 1 and the unordered pass 2; from
 // kSampleMin on, the sample polygon first, then one fused read (pass 1 plus
-// the polygon test), the octagon build, and the octagon test on the
-// candidates (or, without a usable polygon, the unordered pass 2).
+// the polygon test) and the octagon test on the candidates, whose
+// workgroups build the octagon from the pass's partials themselves (or,
+// without a usable polygon, the unordered pass 2 with that octagon).
 ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
                      uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
                      hipStream_t st, Rec* surv_rec = nullptr, Rec* cand = nullptr) {
@@ -223,7 +227,7 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
   if (fused) {
     {
       ProfScope p(ctx, st, "sample_poly");
-      e = launch_sample_poly(d_xy, n, scratch, poly, st);
+      e = launch_sample_poly(d_xy, n, scratch, poly, count_out, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "sample polygon launch");
     {
@@ -237,16 +241,17 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
     e = launch_reduce8(d_xy, n, head, partials, part_bad, g1, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce8 launch");
   }
-  {
+  if (!fused) {  // after a fused pass the candidate test builds the octagon itself
     ProfScope p(ctx, st, "oct_build");
     e = launch_oct_build(partials, part_bad, g1, hdr, res, at<uint64_t>(ws, L.tstat), g2, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
   }
-  if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
   {
     ProfScope p(ctx, st, fused ? "cand_filter" : "filter_compact");
     if (surv_rec)
       e = launch_filter_rec(d_xy, n, head, hdr, g1, surv_rec, count_out, poly, cand, scratch,
-                            &res->ncand, &res->mode, st);
+                            &res->ncand, &res->mode, fused ? partials : nullptr, part_bad, g1,
+                            res, st);
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);

@@ -238,15 +238,14 @@ __device__ void octagon_wave(const Keys& k, Octagon& o, uint32_t* vidx, uint32_t
   }
 }
 
-// Wave 0 of k_oct_build: the octagon of the single set, then the per-call
-// counters used by the kernels that follow in stream order.
-__device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint32_t dom_bad) {
+// One wave: the per-call counters used by the kernels that follow in stream
+// order (the survivor count too when `count`).
+__device__ void reset_call_state(Header* hdr, Result* res, bool count) {
   const int lane = threadIdx.x & 63;
-  octagon_wave(k, hdr->oct, hdr->vidx, dom_bad);
   if (lane == 0) {
     hdr->tile_ctr = 0;
     hdr->dom_bad = 0;
-    hdr->count = 0;
+    if (count) hdr->count = 0;
     hdr->col_arrive = 0;
     res->status = RES_PENDING;
     res->h = 0;
@@ -255,6 +254,13 @@ __device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint
   }
   for (int r = lane; r < kMaxRounds; r += 64) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
   if (lane < 4) res->win_cnt[lane] = 0;
+}
+
+// Wave 0 of k_oct_build: the octagon of the single set, then the per-call
+// counters.
+__device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint32_t dom_bad) {
+  octagon_wave(k, hdr->oct, hdr->vidx, dom_bad);
+  reset_call_state(hdr, res, true);
 }
 
 // Pass 1: persistent grid. Each wave streams batches of kU rows of 64 pairs
@@ -689,10 +695,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy,
 // wave and 64 candidates). Run by k_filter_hull's grid after a fused pass
 // with a usable sample polygon.
 __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __restrict__ cand_count,
-                            Header* __restrict__ hdr, Rec* __restrict__ surv,
-                            uint32_t* __restrict__ count_out, uint32_t* __restrict__ ncand_out) {
+                            const Octagon* __restrict__ o, uint32_t* __restrict__ vidx,
+                            Rec* __restrict__ surv, uint32_t* __restrict__ count_out,
+                            uint32_t* __restrict__ ncand_out) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *ncand_out = *cand_count;
-  const Octagon* __restrict__ o = &hdr->oct;
   if (o->status != 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = kCountDomain;
     return;
@@ -704,11 +710,6 @@ __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __rest
   __shared__ uint32_t s_base;
   const uint32_t m = *cand_count;
   if (blockIdx.x * kBlock * 4 >= m) return;  // no records for this workgroup
-  // The octagon in LDS: one global read per workgroup, not one per record.
-  __shared__ Octagon s_oct;
-  if (threadIdx.x < sizeof(Octagon) / 4)
-    reinterpret_cast<uint32_t*>(&s_oct)[threadIdx.x] = reinterpret_cast<const uint32_t*>(o)[threadIdx.x];
-  __syncthreads();
   auto rounds = [&](auto kr_tag) {
     constexpr uint32_t KR = decltype(kr_tag)::value;
     constexpr uint32_t kChunk = kBlock * KR;
@@ -725,7 +726,7 @@ __device__ void cand_filter(const Rec* __restrict__ cand, const uint32_t* __rest
       for (uint32_t j = 0; j < KR; ++j) {
         const uint32_t i = s0 + j * kBlock + threadIdx.x;
         if (i < m && classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF),
-                                     r[j].i, &s_oct, hdr->vidx).keep) {
+                                     r[j].i, o, vidx).keep) {
           km |= 1u << j;
           ++cnt;
         }
@@ -762,20 +763,51 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
                                                         const uint32_t* __restrict__ cand_count,
                                                         uint32_t* __restrict__ ncand_out,
                                                         const uint32_t* __restrict__ mode_in,
-                                                        uint32_t* __restrict__ mode_out) {
+                                                        uint32_t* __restrict__ mode_out,
+                                                        const double* __restrict__ partials,
+                                                        const uint32_t* __restrict__ part_bad,
+                                                        uint32_t nparts, Result* __restrict__ res) {
+  // The octagon lives in LDS: one read (or one build) per workgroup, not a
+  // global read per tested point. The smallest index per vertex is not used
+  // on the hull path (the hull keeps the smallest index of equal points
+  // itself), so vidx is workgroup-local.
+  __shared__ Octagon s_oct;
+  __shared__ uint32_t s_vidx[8];
+  const bool use_cand = gate && gate->nv >= 3;
+  if (partials) {
+    // After a fused pass every workgroup with work combines the pass's
+    // partials and builds the octagon itself (no separate launch);
+    // workgroup 0 publishes it (later kernels check its status) and resets
+    // the per-call counters; the survivor count was reset before the pass.
+    if (use_cand && blockIdx.x != 0 && blockIdx.x * kBlock * 4 >= *cand_count) return;
+    Keys k;
+    const uint32_t bad = combine_partials(partials, part_bad, nparts, k);
+    if (threadIdx.x < 64) octagon_wave(k, s_oct, s_vidx, bad);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < sizeof(Octagon) / 4)
+        reinterpret_cast<uint32_t*>(&hdr->oct)[threadIdx.x] = reinterpret_cast<const uint32_t*>(&s_oct)[threadIdx.x];
+      if (threadIdx.x < 64) reset_call_state(hdr, res, false);
+    }
+  } else {
+    if (threadIdx.x < sizeof(Octagon) / 4)
+      reinterpret_cast<uint32_t*>(&s_oct)[threadIdx.x] = reinterpret_cast<const uint32_t*>(&hdr->oct)[threadIdx.x];
+    if (threadIdx.x < 8) s_vidx[threadIdx.x] = 0xFFFFFFFFu;
+    __syncthreads();
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) *mode_out = mode_in ? *mode_in : 0u;
   // After a fused pass with a usable sample polygon only its candidates need
   // the octagon test; otherwise this is the second read of the points.
-  if (gate && gate->nv >= 3) {
-    cand_filter(cand, cand_count, hdr, surv, count_out, ncand_out);
+  if (use_cand) {
+    cand_filter(cand, cand_count, &s_oct, s_vidx, surv, count_out, ncand_out);
     return;
   }
   constexpr int kCapW = StageCap<Rec>::value;
   __shared__ Rec s_buf[kWaves][kCapW];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
-  const Octagon* __restrict__ o = &hdr->oct;
-  uint32_t* __restrict__ vidx = hdr->vidx;
+  const Octagon* __restrict__ o = &s_oct;
+  uint32_t* __restrict__ vidx = s_vidx;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
   if (o->status != 0) {
@@ -1539,11 +1571,13 @@ hipError_t launch_filter(const float* xy, uint32_t n, uint32_t head, Header* hdr
 hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header* hdr,
                              uint32_t blocks, Rec* surv, uint32_t* count_out,
                              const SamplePoly* gate, const Rec* cand, const void* scratch,
-                             uint32_t* ncand_out, uint32_t* mode_out, hipStream_t st) {
+                             uint32_t* ncand_out, uint32_t* mode_out, const double* partials,
+                             const uint32_t* part_bad, uint32_t nparts, Result* res,
+                             hipStream_t st) {
   const SampleDirs* sd = static_cast<const SampleDirs*>(scratch);
   hipLaunchKernelGGL(k_filter_hull, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, surv,
                      count_out, gate, cand, sd ? &sd->cand : nullptr, ncand_out,
-                     sd ? &sd->mode : nullptr, mode_out);
+                     sd ? &sd->mode : nullptr, mode_out, partials, part_bad, nparts, res);
   return hipGetLastError();
 }
 

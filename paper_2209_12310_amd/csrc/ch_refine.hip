@@ -88,12 +88,14 @@ static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256 + size_t(kLutBins
               "workspace slot of the direction maxima");
 
 __global__ __launch_bounds__(kBlock) void k_sample_dirs(const float* __restrict__ xy, uint32_t n,
-                                                        SampleDirs* __restrict__ sd) {
+                                                        SampleDirs* __restrict__ sd,
+                                                        uint32_t* __restrict__ count0) {
   static_assert(kPolyMax == 2 * kBlock, "a direction and its opposite per thread");
   __shared__ int2 sp[kSamplePer];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sd->arrive = 0;  // for k_sample_reduce
     sd->cand = 0;    // for the fused pass
+    *count0 = 0;     // survivors of the candidates' octagon test, two launches on
   }
   const uint32_t k0 = blockIdx.x * kSamplePer;
   for (uint32_t q = threadIdx.x; q < kSamplePer; q += kBlock)
@@ -155,9 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_sample_reduce(const float* __restric
 }
 
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
-                              hipStream_t st) {
+                              uint32_t* count0, hipStream_t st) {
   SampleDirs* sd = static_cast<SampleDirs*>(scratch);
-  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd);
+  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd, count0);
   hipLaunchKernelGGL(k_sample_reduce, dim3(kSampleReduceBlocks), dim3(kBlock), 0, st, xy, n, sd, poly);
   return hipGetLastError();
 }
