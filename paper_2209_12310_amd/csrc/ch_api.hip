@@ -43,7 +43,8 @@ hipError_t launch_filter_rec(const float* xy, uint32_t n, uint32_t head, Header*
                              const uint32_t* part_bad, uint32_t nparts, Result* res,
                              hipStream_t st);
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
-                             uint32_t* res_idx, const Octagon* oct, hipStream_t st);
+                             uint32_t* res_idx, const Octagon* oct, Result* host,
+                             uint32_t* host_idx, uint32_t host_n, hipStream_t st);
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
                              Rec* out_rec, uint32_t* out_count, uint32_t* tile_ctr,
                              hipStream_t st);
@@ -92,6 +93,7 @@ struct ch_ctx {
   uint32_t fused_max_blocks = 512;
   uint32_t narrow_blocks = 256;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
+  unsigned char* pinned_dev = nullptr;  // its device address (null: copied, not written directly)
   std::string err;
   ch_hull_info last{};  // counts of the last successful ch_hull
   // Batch-mode parameters: fixed ones (ch_batch_params_set), else the tuned
@@ -451,9 +453,15 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
     if (v >= 1 && v <= kReduceMaxBlocks) ctx->narrow_blocks = (uint32_t)v;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kResBytes + 4 * kPinIdx,
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete ctx;
     return CH_E_NOMEM;
+  }
+  {
+    // The block hull writes the result block straight into this buffer.
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, ctx->pinned, 0) == hipSuccess) ctx->pinned_dev = static_cast<unsigned char*>(dp);
+    else (void)hipGetLastError();
   }
   ctx->batch = default_batch_params(ctx->cu_count);
   {
@@ -555,14 +563,22 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
   };
+  // After the block hull: it wrote the result block to the pinned buffer
+  // itself when that buffer is device-mapped.
+  Result* dres_host = reinterpret_cast<Result*>(ctx->pinned_dev);
+  uint32_t* didx_host = ctx->pinned_dev ? reinterpret_cast<uint32_t*>(ctx->pinned_dev + kResBytes) : nullptr;
+  auto fetch_final = [&]() -> hipError_t {
+    if (!ctx->pinned_dev) return fetch();
+    return hipStreamSynchronize(st);
+  };
 
   hipError_t e;
   {
     ProfScope p(ctx, st, "hull_final");
-    e = launch_hull_final(srec, &hdr->count, res, res_idx, &hdr->oct, st);
+    e = launch_hull_final(srec, &hdr->count, res, res_idx, &hdr->oct, dres_host, didx_host, pin_n, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
-  if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull final");
+  if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "hull final");
   prof_collect(ctx, st);
   if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
   ch_hull_info info{};
@@ -592,10 +608,11 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     if (e != hipSuccess) return hip_fail(ctx, e, "hull round launch");
     {
       ProfScope p(ctx, st, "hull_final");
-      e = launch_hull_final(rec[round & 1], &res->round_cnt[round + 1], res, res_idx, &hdr->oct, st);
+      e = launch_hull_final(rec[round & 1], &res->round_cnt[round + 1], res, res_idx, &hdr->oct,
+                            dres_host, didx_host, pin_n, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
-    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "hull round");
+    if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "hull round");
     prof_collect(ctx, st);
     last_list = round & 1;
     ++round;

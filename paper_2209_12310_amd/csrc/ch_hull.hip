@@ -24,6 +24,8 @@
 //
 // Every orientation test is exact: coordinate differences are below 2^20, so
 // the products are below 2^40 and fp64 holds them and their difference.
+#include <cstddef>
+
 #include "ch_device.hpp"
 
 namespace chk {
@@ -726,17 +728,38 @@ __device__ __forceinline__ Rec hull_elem(const HullSmem<T>& sm, uint32_t k, uint
   return r;
 }
 
+// The result block for the host, written straight into pinned host memory
+// mapped for the device (no copy launch): the device Result with this
+// call's status, h and input count.
+__device__ void publish_result(const Result* __restrict__ res, Result* __restrict__ host,
+                               uint32_t status, uint32_t h, uint32_t cin) {
+  constexpr uint32_t kWords = sizeof(Result) / 4;
+  for (uint32_t t = threadIdx.x; t < kWords; t += kBlock) {
+    uint32_t v = reinterpret_cast<const uint32_t*>(res)[t];
+    if (t == offsetof(Result, status) / 4) v = status;
+    else if (t == offsetof(Result, h) / 4) v = h;
+    else if (t == offsetof(Result, cin) / 4) v = cin;
+    reinterpret_cast<uint32_t*>(host)[t] = v;
+  }
+}
+
 // One workgroup: the hull of all candidates when they fit (status DONE),
-// otherwise status MORE with the candidate count in res->cin.
+// otherwise status MORE with the candidate count in res->cin. With `host`
+// (pinned, device-mapped) the result block and the first `host_n` hull
+// indices also go to host memory.
 __global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ in_rec,
                                                        const uint32_t* __restrict__ in_count,
                                                        Result* __restrict__ res,
                                                        uint32_t* __restrict__ res_idx,
-                                                       const Octagon* __restrict__ oct) {
+                                                       const Octagon* __restrict__ oct,
+                                                       Result* __restrict__ host,
+                                                       uint32_t* __restrict__ host_idx,
+                                                       uint32_t host_n) {
   __shared__ HullSmem<kFinalTile> sm;
   CH_MARK(res, 0);
   if (oct->status != 0) {
     if (threadIdx.x == 0) res->status = RES_DOMAIN;
+    if (host) publish_result(res, host, RES_DOMAIN, 0, 0);
     return;
   }
   const uint32_t c = *in_count;
@@ -744,16 +767,22 @@ __global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ i
   if (threadIdx.x == 0) res->cin = c;
   if (c > (uint32_t)kFinalTile) {
     if (threadIdx.x == 0) res->status = RES_MORE;
+    if (host) publish_result(res, host, RES_MORE, 0, c);
     return;
   }
   uint32_t nl, nu;
   const uint32_t h = tile_hull<kFinalTile>(sm, in_rec, 0, c, nl, nu, res);
-  for (uint32_t k = threadIdx.x; k < h; k += kBlock) res_idx[k] = hull_elem(sm, k, nl, nu).i;
+  for (uint32_t k = threadIdx.x; k < h; k += kBlock) {
+    const uint32_t v = hull_elem(sm, k, nl, nu).i;
+    res_idx[k] = v;
+    if (host && k < host_n) host_idx[k] = v;
+  }
   CH_MARK(res, 8);
   if (threadIdx.x == 0) {
     res->h = h;
     res->status = RES_DONE;
   }
+  if (host) publish_result(res, host, RES_DONE, h, c);
 }
 
 // Many workgroups: tiles of kHullTile candidates to tile hulls, appended to
@@ -1081,8 +1110,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_round(const uint64_t* __restri
 // ------------------------------------------------------------- launchers
 
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
-                             uint32_t* res_idx, const Octagon* oct, hipStream_t st) {
-  hipLaunchKernelGGL(k_hull_final, dim3(1), dim3(kBlock), 0, st, in_rec, in_count, res, res_idx, oct);
+                             uint32_t* res_idx, const Octagon* oct, Result* host,
+                             uint32_t* host_idx, uint32_t host_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_hull_final, dim3(1), dim3(kBlock), 0, st, in_rec, in_count, res, res_idx, oct,
+                     host, host_idx, host_n);
   return hipGetLastError();
 }
 

@@ -145,18 +145,31 @@ __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_
   if (lane < kCand) s_red[w][lane] = t;
   __syncthreads();
   __shared__ float s_os, s_ot;
-  if (threadIdx.x == 0) {
-    double best = -1.0, bs = 0.0, bt = 0.0;
-    for (int i = 0; i < kCand && m >= 3; ++i) {
-      double ti = s_red[0][i];
-      for (int q = 1; q < kWaves; ++q) ti = __builtin_fmin(ti, s_red[q][i]);
-      const double si = smax * (1.0 - __builtin_ldexp(1.0, -i - 3));
-      const double a = 4.0 * si * si - 2.0 * (2.0 * si - ti) * (2.0 * si - ti);
-      if (si > 0.0 && ti >= si && a > best) { best = a; bs = si; bt = ti; }
+  if (threadIdx.x < 64) {
+    // Lane i < kCand scores candidate i (its area); the largest wins, the
+    // first of equal ones.
+    double a = -1.0, si = 0.0, ti = 0.0;
+    if (lane < kCand && m >= 3) {
+      ti = s_red[0][lane];
+#pragma unroll
+      for (int q = 1; q < kWaves; ++q) ti = __builtin_fmin(ti, s_red[q][lane]);
+      si = smax * (1.0 - __builtin_ldexp(1.0, -lane - 3));
+      const double ar = 4.0 * si * si - 2.0 * (2.0 * si - ti) * (2.0 * si - ti);
+      if (si > 0.0 && ti >= si) a = ar;
     }
-    // grid units -> float units, shrunk by a relative 2^-20
-    s_os = best > 0.0 ? (float)(bs * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
-    s_ot = best > 0.0 ? (float)(bt * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
+    int win = 0;
+    double best = read_lane(a, 0);
+#pragma unroll
+    for (int i = 1; i < kCand; ++i) {
+      const double ai = read_lane(a, i);
+      if (ai > best) { best = ai; win = i; }
+    }
+    const double bs = read_lane(si, win), bt = read_lane(ti, win);
+    if (lane == 0) {
+      // grid units -> float units, shrunk by a relative 2^-20
+      s_os = best > 0.0 ? (float)(bs * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
+      s_ot = best > 0.0 ? (float)(bt * 0x1p-20 * (1.0 - 0x1p-20)) : 0.0f;
+    }
   }
   __syncthreads();
   const double gs = (double)s_os * 0x1p20, gt = (double)s_ot * 0x1p20;  // exact
