@@ -574,25 +574,50 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
     s_c[d] = ey * (double)ax - ex * (double)ay;
   }
   __syncthreads();
-  // Keep a candidate outside some polygon side, or equal to a vertex (then
-  // on the boundary: no side value below zero and one equal to zero).
+  // Keep a candidate outside some polygon side, or equal to a vertex. The
+  // vertices are wave-uniform (scalar registers): the equality test needs
+  // no branch and no LDS read.
+  int32_t cvx[16], cvy[16];
+#pragma unroll
+  for (int d = 0; d < 16; ++d) {
+    cvx[d] = __builtin_amdgcn_readfirstlane(s_vx[d]);
+    cvy[d] = __builtin_amdgcn_readfirstlane(s_vy[d]);
+  }
+  // Items go in groups of up to four (independent chains side by side); a
+  // group starts only when some item of it exists in the workgroup.
+  constexpr uint32_t kG = E < 4 ? E : 4;
+  const uint32_t ea = (cnt + kBlock - 1) / kBlock;  // items per thread in use (uniform)
   uint32_t keepmask = 0, nkeep = 0;
 #pragma unroll
-  for (uint32_t e = 0; e < E; ++e) {
-    const uint32_t i = threadIdx.x + e * kBlock;
-    if (i < cnt) {
-      const int32_t x = sm.px[i], y = sm.py[i];
-      const double fx = (double)x, fy = (double)y;
-      double mn = __builtin_inf();
+  for (uint32_t e0 = 0; e0 < E; e0 += kG) {
+    if (e0 >= ea) break;
+    int32_t x[kG], y[kG];
+    double fx[kG], fy[kG], mn[kG];
+    bool eq[kG];
 #pragma unroll
-      for (int d = 0; d < 16; ++d)
-        mn = __builtin_fmin(mn, __builtin_fma(s_ex[d], fy, __builtin_fma(s_ney[d], fx, s_c[d])));
-      bool keep = mn < 0.0;
-      if (mn == 0.0) {
+    for (uint32_t u = 0; u < kG; ++u) {
+      const uint32_t i = threadIdx.x + (e0 + u) * kBlock;
+      const uint32_t ii = i < cnt ? i : cnt - 1;
+      x[u] = sm.px[ii];
+      y[u] = sm.py[ii];
+      fx[u] = (double)x[u];
+      fy[u] = (double)y[u];
+      mn[u] = __builtin_inf();
+      eq[u] = false;
+    }
 #pragma unroll
-        for (int d = 0; d < 16; ++d) keep |= (x == s_vx[d]) & (y == s_vy[d]);
+    for (int d = 0; d < 16; ++d) {
+      const double ex = s_ex[d], ney = s_ney[d], c = s_c[d];
+#pragma unroll
+      for (uint32_t u = 0; u < kG; ++u) {
+        mn[u] = __builtin_fmin(mn[u], __builtin_fma(ex, fy[u], __builtin_fma(ney, fx[u], c)));
+        eq[u] |= (x[u] == cvx[d]) & (y[u] == cvy[d]);
       }
-      if (keep) { keepmask |= 1u << e; ++nkeep; }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kG; ++u) {
+      const uint32_t i = threadIdx.x + (e0 + u) * kBlock;
+      if (i < cnt && ((mn[u] < 0.0) | eq[u])) { keepmask |= 1u << (e0 + u); ++nkeep; }
     }
   }
   if (tm) CH_MARK(tm, 10);
