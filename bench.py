@@ -468,7 +468,7 @@ def main() -> int:
                                      "h": int(hull.size)}}
     if not args.no_extra:
         for name in ("uniform_1e8", "annulus_1e8", "uniform_1e6"):
-            out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 2)
+            out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 5)
             torch.cuda.synchronize()
     if not args.no_batch:
         out["batch"] = bench_batch(ctx, max(5, min(args.steps, 20)), 1)
