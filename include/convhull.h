@@ -150,14 +150,10 @@ typedef struct {
 } ch_hull_info;
 ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out);
 
-/* Count values ch_hull_batch writes for a set it could not finish:
- * CH_COUNT_DOMAIN_ERROR (above) for a domain error in that set;
- * CH_COUNT_OVERFLOW when the set's candidates did not shrink to one workgroup
- * within the batch's tile-hull rounds (only possible with thousands of points
- * in convex position; ch_hull handles any set);
- * CH_COUNT_INVALID for every set when the offsets are not non-decreasing from
- * 0 to total_points. */
-#define CH_COUNT_OVERFLOW 0xFFFFFFFEu
+/* Count value ch_hull_batch writes for every set when the offsets are not
+ * non-decreasing from 0 to total_points (a set with a domain error gets
+ * CH_COUNT_DOMAIN_ERROR, above). Every other set gets its hull, whatever its
+ * size or shape. */
 #define CH_COUNT_INVALID 0xFFFFFFFDu
 
 /* Device workspace bytes needed by ch_hull_batch. */

@@ -23,7 +23,6 @@ CH_E_CANCELLED = 8
 CH_E_SHUTDOWN = 9
 CH_E_NOT_FOUND = 10
 CH_COUNT_DOMAIN_ERROR = 0xFFFFFFFF
-CH_COUNT_OVERFLOW = 0xFFFFFFFE
 CH_COUNT_INVALID = 0xFFFFFFFD
 CH_MAX_POINTS = 0x7FFFFFFF
 

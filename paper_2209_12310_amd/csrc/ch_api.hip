@@ -48,15 +48,10 @@ hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
                              Rec* out_rec, uint32_t* out_count, uint32_t* tile_ctr,
                              hipStream_t st);
-hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t max_in,
-                            uint64_t* bot, uint64_t* top, uint32_t* cnt, Rec* lst_lo, Rec* lst_up,
-                            const Octagon* oct, Result* res, hipStream_t st);
-hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl, uint32_t cu,
-                               uint32_t shift, Rec* tmp_lo, Rec* tmp_up, uint32_t* wcnt_lo,
-                               uint32_t* wcnt_up, Rec* dst_lo, Rec* dst_up, Result* res,
-                               hipStream_t st);
-hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
-                              Result* res, uint32_t* res_idx, hipStream_t st);
+hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
+                             uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
+                             uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
+                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st);
 hipError_t launch_read_stream(const void* d_buf, size_t bytes, uint32_t blocks, float* sink,
                               hipStream_t st);
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
@@ -74,8 +69,7 @@ using namespace chk;
 
 namespace {
 
-constexpr uint32_t kPinIdx = 2048;  // hull indices fetched with the result block
-constexpr int kWinShift = 4096 / 2;
+constexpr uint32_t kPinIdx = 16384;  // hull indices the device writes to pinned host memory
 
 struct KStat {
   const char* name;
@@ -631,52 +625,15 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     const uint32_t cin = round ? hres->round_cnt[round] : hres->cin;
     const Rec* lin = round ? rec[last_list] : srec;
     const uint32_t* lcnt = round ? &res->round_cnt[round] : &hdr->count;
-    Rec* lstA = at<Rec>(d_ws, L.lstA);
-    Rec* lstB = at<Rec>(d_ws, L.lstB);
-    const size_t chain_cap = size_t(kColumns) + 2;
-    Rec* Alo = lstA; Rec* Aup = lstA + chain_cap;
-    Rec* Blo = lstB; Rec* Bup = lstB + chain_cap;
-    uint32_t* wcnt = at<uint32_t>(d_ws, L.wcnt);
-    const size_t wstride = chain_cap / 4096 + 4;
     {
-      ProfScope p(ctx, st, "col_build");
-      e = launch_col_build(lin, lcnt, cin, at<uint64_t>(d_ws, L.colbot),
-                           at<uint64_t>(d_ws, L.coltop), at<uint32_t>(d_ws, L.colcnt), Alo, Aup,
-                           &hdr->oct, res, st);
+      ProfScope p(ctx, st, "large_path");
+      e = launch_large_path(lin, lcnt, cin, at<uint64_t>(d_ws, L.colbot), at<uint64_t>(d_ws, L.coltop),
+                            at<uint32_t>(d_ws, L.colcnt), at<Rec>(d_ws, L.lstA),
+                            at<Rec>(d_ws, L.lstB), at<uint32_t>(d_ws, L.wcnt), &hdr->oct, res,
+                            res_idx, dres_host, didx_host, pin_n, st);
     }
-    if (e != hipSuccess) return hip_fail(ctx, e, "column build launch");
-    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "column build");
-    prof_collect(ctx, st);
-    uint32_t cl = hres->lcount, cu = hres->ucount;
-    int stall = 0, parity = 0;
-    for (uint64_t it = 0;; ++it) {
-      if (it > (uint64_t)4 * (cl + cu) + 8) return fail(ctx, CH_E_DEVICE, "window rounds did not settle");
-      if (cl <= 4096 && cu <= 4096) {
-        ProfScope p(ctx, st, "large_final");
-        e = launch_large_final(Alo, Aup, cl, cu, 1, res, res_idx, st);
-        break;
-      }
-      {
-        ProfScope p(ctx, st, "window_round");
-        e = launch_window_round(Alo, Aup, cl, cu, parity ? kWinShift : 0, Blo, Bup, wcnt,
-                                wcnt + wstride, Alo, Aup, res, st);
-      }
-      if (e != hipSuccess) return hip_fail(ctx, e, "window round launch");
-      if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "window round");
-      prof_collect(ctx, st);
-      const uint32_t nl = hres->lcount, nu = hres->ucount;
-      stall = (nl == cl && nu == cu) ? stall + 1 : 0;
-      cl = nl;
-      cu = nu;
-      if (stall >= 2) {
-        ProfScope p(ctx, st, "large_final");
-        e = launch_large_final(Alo, Aup, cl, cu, 0, res, res_idx, st);
-        break;
-      }
-      parity ^= 1;
-    }
-    if (e != hipSuccess) return hip_fail(ctx, e, "large final launch");
-    if ((e = fetch()) != hipSuccess) return hip_fail(ctx, e, "large final");
+    if (e != hipSuccess) return hip_fail(ctx, e, "large path launch");
+    if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "large path");
     prof_collect(ctx, st);
     if (hres->status != RES_DONE) return fail(ctx, CH_E_DEVICE, "large hull status %u", hres->status);
   }

@@ -253,7 +253,7 @@ __device__ void reset_call_state(Header* hdr, Result* res, bool count) {
     res->ncand = 0;
   }
   for (int r = lane; r < kMaxRounds; r += 64) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
-  if (lane < 4) res->win_cnt[lane] = 0;
+  if (lane < 2) { res->pack_cnt[lane] = 0; res->fold_cnt[lane] = 0; }
 }
 
 // Wave 0 of k_oct_build: the octagon of the single set, then the per-call

@@ -30,13 +30,6 @@
 
 namespace chk {
 
-#ifdef CH_PHASE_TIMING
-#define CH_MARK(res, k) \
-  do { if (threadIdx.x == 0) (res)->tphase[k] = __builtin_amdgcn_s_memrealtime(); } while (0)
-#else
-#define CH_MARK(res, k) do { } while (0)
-#endif
-
 // Sequential monotone chain of src[s0, s0+len) onto a stack at dst[s0...];
 // src may equal dst (the stack never overtakes the read position).
 template <bool LOWER>
@@ -523,14 +516,12 @@ __device__ __forceinline__ constexpr int dir_y(int d) {
 // tile_hull_core expects the `cnt` candidates in sm.px/py/pi (visible to the
 // whole workgroup); tile_hull loads them from records first.
 template <int T>
-__device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, uint32_t& nu,
-                                   Result* tm = nullptr) {
+__device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, uint32_t& nu) {
   constexpr uint32_t E = T / kBlock;  // items per thread: i = threadIdx.x + e * kBlock
   __shared__ uint64_t s_ext[kWaves][16];
   __shared__ int32_t s_vx[16], s_vy[16];
   __shared__ double s_ex[16], s_ney[16], s_c[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (tm) CH_MARK(tm, 2);
   // Extreme position per direction: max of (dot, -position) per thread, then
   // per wave (transposed DPP exchange: lane l ends with direction l mod 16),
   // then over the waves.
@@ -551,7 +542,6 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
     if (lane < 16) s_ext[w][lane] = m;
   }
   __syncthreads();
-  if (tm) CH_MARK(tm, 9);
   // Thread d takes vertices d and d+1 and writes side d as
   // orient(v_d, v_(d+1), p) = ex * py + ney * px + c, exact in fp64 (each
   // product below 2^42, each partial sum below 2^43).
@@ -620,10 +610,8 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
       if (i < cnt && ((mn[u] < 0.0) | eq[u])) { keepmask |= 1u << (e0 + u); ++nkeep; }
     }
   }
-  if (tm) CH_MARK(tm, 10);
   uint32_t kept;
   uint32_t kpos = block_excl_scan(nkeep, kept);
-  if (tm) CH_MARK(tm, 11);
   uint32_t P2 = kBlock;
   while (P2 < kept) P2 <<= 1;
 #pragma unroll
@@ -638,13 +626,10 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
   for (uint32_t i = kept + threadIdx.x; i < P2; i += kBlock) sm.a.key[i] = ~0ull;
   cnt = kept;
   __syncthreads();
-  if (tm) CH_MARK(tm, 3);
   if (kept >= 1 && kept <= 2 * kSmallChain && small_chains<T>(sm, kept, nl, nu)) {
-    if (tm) CH_MARK(tm, 6);
     return nl + (nu > 2 ? nu - 2 : 0);
   }
   bitonic_sort(sm.a.key, P2);
-  if (tm) CH_MARK(tm, 4);
   // One entry per distinct coordinate, carrying the smallest index.
   const uint32_t E2 = P2 / kBlock;
   const uint32_t j0 = threadIdx.x * E2;
@@ -672,7 +657,6 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
     }
   }
   __syncthreads();
-  if (tm) CH_MARK(tm, 5);
   if (u == 0) { nl = nu = 0; return 0; }
   // Split by the line from the lexicographic minimum to the maximum: a point
   // strictly above it cannot be on the lower chain, one strictly below cannot
@@ -711,14 +695,12 @@ __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, 
   }
   dual_chain<maxc<T>()>(sm.px, sm.py, sm.pi, ul, sm.a.u.ux, sm.a.u.uy, sm.b.ui, uu, sm.cnt,
                         sm.cnt2, sm.wij, sm.wij2, nl, nu);
-  if (tm) CH_MARK(tm, 6);
-  if (tm) CH_MARK(tm, 7);
   return nl + (nu > 2 ? nu - 2 : 0);
 }
 
 template <int T>
 __device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, uint32_t base,
-                              uint32_t cnt, uint32_t& nl, uint32_t& nu, Result* tm = nullptr) {
+                              uint32_t cnt, uint32_t& nl, uint32_t& nu) {
   // four loads in flight per thread (clamped to the last record), then the stores
   constexpr uint32_t kLd = 4;
   for (uint32_t i0 = 0; i0 < cnt; i0 += kLd * kBlock) {
@@ -735,7 +717,7 @@ __device__ uint32_t tile_hull(HullSmem<T>& sm, const Rec* __restrict__ in_rec, u
     }
   }
   __syncthreads();
-  return tile_hull_core<T>(sm, cnt, nl, nu, tm);
+  return tile_hull_core<T>(sm, cnt, nl, nu);
 }
 
 // Element k of the counter-clockwise hull: the lower chain, then the upper
@@ -781,14 +763,12 @@ __global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ i
                                                        uint32_t* __restrict__ host_idx,
                                                        uint32_t host_n) {
   __shared__ HullSmem<kFinalTile> sm;
-  CH_MARK(res, 0);
   if (oct->status != 0) {
     if (threadIdx.x == 0) res->status = RES_DOMAIN;
     if (host) publish_result(res, host, RES_DOMAIN, 0, 0);
     return;
   }
   const uint32_t c = *in_count;
-  CH_MARK(res, 1);
   if (threadIdx.x == 0) res->cin = c;
   if (c > (uint32_t)kFinalTile) {
     if (threadIdx.x == 0) res->status = RES_MORE;
@@ -796,13 +776,12 @@ __global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ i
     return;
   }
   uint32_t nl, nu;
-  const uint32_t h = tile_hull<kFinalTile>(sm, in_rec, 0, c, nl, nu, res);
+  const uint32_t h = tile_hull<kFinalTile>(sm, in_rec, 0, c, nl, nu);
   for (uint32_t k = threadIdx.x; k < h; k += kBlock) {
     const uint32_t v = hull_elem(sm, k, nl, nu).i;
     res_idx[k] = v;
     if (host && k < host_n) host_idx[k] = v;
   }
-  CH_MARK(res, 8);
   if (threadIdx.x == 0) {
     res->h = h;
     res->status = RES_DONE;
@@ -932,33 +911,35 @@ __global__ __launch_bounds__(kBlock) void k_col_emit(const uint64_t* __restrict_
 }
 
 constexpr int kWin = 4096;
+// Windows per column list (a list holds at most kColumns + 2 records).
+constexpr uint32_t kWinPerList = (kColumns + 2 + kWin - 1) / kWin;
 
 template <bool LOWER>
 __device__ uint32_t window_chain(WinSmem<kWin>& sm, uint32_t u) {
   return par_chain<LOWER, maxc<kWin>()>(sm.px, sm.py, sm.pi, sm.px, sm.py, sm.pi, u, sm.cnt, sm.wij);
 }
 
-// One window round over the lower list (blocks [0, nwl)) and the upper list
-// (blocks [nwl, nwl + nwu)). Window k covers [k*W - shift, (k+1)*W - shift).
-// Its chain is written back at the window's start in dst; its length in wcnt.
+// Window chains of the two column lists: workgroup b < kWinPerList takes
+// window b of the lower list, the others window b - kWinPerList of the upper
+// list. The list lengths come from the column emission (res->lcount,
+// res->ucount); a workgroup past its list's end returns at once. Window k
+// covers [k*kWin, (k+1)*kWin); its chain goes to the window's start in dst,
+// its length to wcnt[b].
 __global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src_lo,
-                                                   const Rec* __restrict__ src_up, uint32_t cl,
-                                                   uint32_t cu, uint32_t shift, uint32_t nwl,
+                                                   const Rec* __restrict__ src_up,
+                                                   const Result* __restrict__ res,
                                                    Rec* __restrict__ dst_lo,
                                                    Rec* __restrict__ dst_up,
-                                                   uint32_t* __restrict__ wcnt_lo,
-                                                   uint32_t* __restrict__ wcnt_up) {
+                                                   uint32_t* __restrict__ wcnt) {
   __shared__ WinSmem<kWin> sm;
-  const bool lower = blockIdx.x < nwl;
-  const uint32_t k = lower ? blockIdx.x : blockIdx.x - nwl;
-  const uint32_t c = lower ? cl : cu;
+  const bool lower = blockIdx.x < kWinPerList;
+  const uint32_t k = lower ? blockIdx.x : blockIdx.x - kWinPerList;
+  const uint32_t c = lower ? res->lcount : res->ucount;
+  const uint32_t lo = k * (uint32_t)kWin;
+  if (lo >= c) return;
+  const uint32_t u = c - lo < (uint32_t)kWin ? c - lo : (uint32_t)kWin;
   const Rec* src = lower ? src_lo : src_up;
   Rec* dst = lower ? dst_lo : dst_up;
-  const int64_t s = (int64_t)k * kWin - shift;
-  const uint32_t lo = s < 0 ? 0u : (uint32_t)s;
-  const uint64_t e = (uint64_t)(s + kWin);
-  const uint32_t hi = e > c ? c : (uint32_t)e;
-  const uint32_t u = hi > lo ? hi - lo : 0;
   for (uint32_t i = threadIdx.x; i < u; i += kBlock) {
     const Rec r = src[lo + i];
     sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
@@ -970,81 +951,269 @@ __global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src_l
     r.x = sm.px[i]; r.y = sm.py[i]; r.i = sm.pi[i]; r.pad = 0;
     dst[lo + i] = r;
   }
-  if (threadIdx.x == 0) (lower ? wcnt_lo : wcnt_up)[k] = h;
+  if (threadIdx.x == 0) wcnt[blockIdx.x] = h;
 }
 
-// Concatenate the window chains in order: window k's chain moves to the sum
-// of the lengths before it.
+// Concatenate the window chains of each list in order (same grid as
+// k_window): window k's chain moves to the sum of the chain lengths before
+// it; the last window of a list records the packed length in res->pack_cnt.
 __global__ __launch_bounds__(kBlock) void k_window_pack(const Rec* __restrict__ src_lo,
                                                         const Rec* __restrict__ src_up,
-                                                        uint32_t shift, uint32_t nwl,
-                                                        const uint32_t* __restrict__ wcnt_lo,
-                                                        const uint32_t* __restrict__ wcnt_up,
+                                                        const uint32_t* __restrict__ wcnt,
+                                                        Result* __restrict__ res,
                                                         Rec* __restrict__ dst_lo,
-                                                        Rec* __restrict__ dst_up,
-                                                        Result* __restrict__ res, uint32_t nwu) {
-  __shared__ uint32_t s_off;
-  const bool lower = blockIdx.x < nwl;
-  const uint32_t k = lower ? blockIdx.x : blockIdx.x - nwl;
-  const uint32_t* wc = lower ? wcnt_lo : wcnt_up;
-  if (threadIdx.x == 0) {
-    uint32_t o = 0;
-    for (uint32_t i = 0; i < k; ++i) o += wc[i];
-    s_off = o;
-    const uint32_t nw = lower ? nwl : nwu;
-    if (k == nw - 1) (lower ? res->lcount : res->ucount) = o + wc[k];
-  }
-  __syncthreads();
-  const int64_t s = (int64_t)k * kWin - shift;
-  const uint32_t lo = s < 0 ? 0u : (uint32_t)s;
+                                                        Rec* __restrict__ dst_up) {
+  const bool lower = blockIdx.x < kWinPerList;
+  const uint32_t k = lower ? blockIdx.x : blockIdx.x - kWinPerList;
+  const uint32_t c = lower ? res->lcount : res->ucount;
+  const uint32_t lo = k * (uint32_t)kWin;
+  if (lo >= c) return;
+  const uint32_t* wc = wcnt + (lower ? 0u : kWinPerList);
+  uint32_t part = 0;
+  for (uint32_t i = threadIdx.x; i < k; i += kBlock) part += wc[i];
+  uint32_t off;
+  block_excl_scan(part, off);
   const uint32_t h = wc[k];
+  if (threadIdx.x == 0 && c - lo <= (uint32_t)kWin) res->pack_cnt[lower ? 0 : 1] = off + h;
   const Rec* src = lower ? src_lo : src_up;
   Rec* dst = lower ? dst_lo : dst_up;
-  for (uint32_t i = threadIdx.x; i < h; i += kBlock) dst[s_off + i] = src[lo + i];
+  for (uint32_t i = threadIdx.x; i < h; i += kBlock) dst[off + i] = src[lo + i];
 }
 
-// Final output of the large-hull path. When both lists fit one window the
-// chains are computed here (single=1); otherwise the lists already are the
-// chains. Writes the counter-clockwise hull to res_idx.
-__global__ __launch_bounds__(kBlock) void k_large_final(const Rec* __restrict__ lo_lst,
-                                                        const Rec* __restrict__ up_lst,
-                                                        uint32_t cl, uint32_t cu, int single,
-                                                        Result* __restrict__ res,
-                                                        uint32_t* __restrict__ res_idx) {
-  __shared__ WinSmem<kWin> sm;
-  uint32_t nl = cl, nu = cu;
-  if (single) {
-    for (uint32_t i = threadIdx.x; i < cl; i += kBlock) {
-      const Rec r = lo_lst[i];
-      sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
+// ------------------------------------------------ the chain of a long list
+//
+// One workgroup computes Andrew's chain (the lower one for LOWER, else the
+// upper one) of the m records in[0..m), sorted by (x, y) with distinct
+// coordinates, as a stack in out[0..r), and returns r. The list is read in
+// batches of up to kWin records; each batch is chained in LDS (par_chain),
+// then joined to the stack: wave 0 walks from the junction, popping the
+// stack's tail and the batch chain's head exactly as Andrew's scan pops when
+// it reaches the batch (both sides are chains already, so only their ends
+// can pop), 64 candidate positions per step; the rest of the batch chain is
+// appended. out may equal in: the stack never holds more records than have
+// been read.
+template <bool LOWER>
+__device__ uint32_t fold_chain(WinSmem<kWin>& sm, const Rec* in, uint32_t m, Rec* out) {
+  __shared__ uint32_t s_keep, s_from;
+  const int lane = threadIdx.x & 63;
+  uint32_t r = 0;
+  for (uint32_t pos = 0; pos < m; pos += kWin) {
+    const uint32_t t = m - pos < (uint32_t)kWin ? m - pos : (uint32_t)kWin;
+    __syncthreads();  // the previous batch is appended; sm is free
+    for (uint32_t i = threadIdx.x; i < t; i += kBlock) {
+      const Rec q = in[pos + i];
+      sm.px[i] = q.x; sm.py[i] = q.y; sm.pi[i] = q.i;
     }
     __syncthreads();
-    nl = window_chain<true>(sm, cl);
-    for (uint32_t i = threadIdx.x; i < nl; i += kBlock) res_idx[i] = sm.pi[i];
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < cu; i += kBlock) {
-      const Rec r = up_lst[i];
-      sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
+    const uint32_t nc = window_chain<LOWER>(sm, t);
+    if (threadIdx.x < 64) {
+      int i = (int)r - 1;  // stack top
+      uint32_t j = 0;      // head of the batch chain
+      if (r > 0) {
+        bool moved = true;
+        while (moved) {
+          moved = false;
+          // Pop the stack's top while it does not turn the right way
+          // towards the batch chain's head (stack positions i, i-1, ...).
+          const int32_t cx = sm.px[j], cy = sm.py[j];
+          while (i >= 1) {
+            const int q = i - lane;
+            bool good = true;  // position 0 is never popped
+            if (q >= 1) {
+              const Rec a = out[q - 1], b = out[q];
+              good = !bad_turn<LOWER>(a.x, a.y, b.x, b.y, cx, cy);
+            }
+            const uint64_t gm = __ballot(good);
+            if (gm) {
+              const int f = __builtin_ctzll(gm);
+              if (f) { i -= f; moved = true; }
+              break;
+            }
+            i -= 64;
+            moved = true;
+          }
+          // Pop the batch chain's head while the stack top, it and its
+          // successor do not turn the right way.
+          const Rec s = out[i];
+          while (j + 1 < nc) {
+            const uint32_t q = j + (uint32_t)lane;
+            bool good = true;  // the batch chain's last point is never popped
+            if (q + 1 < nc) good = !bad_turn<LOWER>(s.x, s.y, sm.px[q], sm.py[q], sm.px[q + 1], sm.py[q + 1]);
+            const uint64_t gm = __ballot(good);
+            if (gm) {
+              const int f = __builtin_ctzll(gm);
+              if (f) { j += (uint32_t)f; moved = true; }
+              break;
+            }
+            j += 64;
+            moved = true;
+          }
+        }
+      }
+      if (lane == 0) { s_keep = (uint32_t)(i + 1); s_from = j; }
     }
     __syncthreads();
-    nu = window_chain<false>(sm, cu);
-    for (uint32_t k = threadIdx.x; k + 2 < nu; k += kBlock) res_idx[nl + k] = sm.pi[nu - 2 - k];
-  } else {
-    for (uint32_t i = threadIdx.x; i < nl; i += kBlock) res_idx[i] = lo_lst[i].i;
-    for (uint32_t k = threadIdx.x; k + 2 < nu; k += kBlock) res_idx[nl + k] = up_lst[nu - 2 - k].i;
+    const uint32_t keep = s_keep, from = s_from;
+    for (uint32_t k = threadIdx.x; from + k < nc; k += kBlock) {
+      Rec q;
+      q.x = sm.px[from + k]; q.y = sm.py[from + k]; q.i = sm.pi[from + k]; q.pad = 0;
+      out[keep + k] = q;
+    }
+    r = keep + (nc - from);
   }
+  __syncthreads();
+  return r;
+}
+
+// Two workgroups: the lower chain of the packed lower list (workgroup 0) and
+// the upper chain of the packed upper list (workgroup 1), each in place.
+__global__ __launch_bounds__(kBlock) void k_fold(Rec* __restrict__ lst_lo, Rec* __restrict__ lst_up,
+                                                 Result* __restrict__ res) {
+  __shared__ WinSmem<kWin> sm;
+  const bool lower = blockIdx.x == 0;
+  const uint32_t m = res->pack_cnt[lower ? 0 : 1];
+  const uint32_t r = lower ? fold_chain<true>(sm, lst_lo, m, lst_lo)
+                           : fold_chain<false>(sm, lst_up, m, lst_up);
+  if (threadIdx.x == 0) res->fold_cnt[lower ? 0 : 1] = r;
+}
+
+// Final output of the large-hull path: the counter-clockwise hull (the lower
+// chain, then the upper chain backwards without its end points) to res_idx,
+// status and h to the result block; with `host` (pinned, device-mapped) the
+// result block and the first host_n indices also go to host memory.
+__global__ __launch_bounds__(kBlock) void k_large_out(const Rec* __restrict__ lo,
+                                                      const Rec* __restrict__ up,
+                                                      Result* __restrict__ res,
+                                                      uint32_t* __restrict__ res_idx,
+                                                      Result* __restrict__ host,
+                                                      uint32_t* __restrict__ host_idx,
+                                                      uint32_t host_n) {
+  const uint32_t nl = res->fold_cnt[0], nu = res->fold_cnt[1], cin = res->cin;
+  const uint32_t h = nl + (nu > 2 ? nu - 2 : 0);
+  for (uint32_t k = threadIdx.x; k < h; k += kBlock) {
+    const uint32_t v = k < nl ? lo[k].i : up[nu - 2 - (k - nl)].i;
+    res_idx[k] = v;
+    if (host && k < host_n) host_idx[k] = v;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    res->h = nl + (nu > 2 ? nu - 2 : 0);
+    res->h = h;
     res->status = RES_DONE;
   }
+  if (host) publish_result(res, host, RES_DONE, h, cin);
+}
+
+// ------------------------------------- batch: sets with many candidates left
+//
+// A set whose candidates did not shrink to one workgroup within the tile-hull
+// rounds (thousands of points in convex position, or close to a smooth curve)
+// gets its hull from one workgroup here, by the column rule of the large-hull
+// path: only the lowest and the highest candidate of a grid column can be a
+// strict hull vertex. The set's columns [xmin, xmax] are taken in chunks of
+// kLdsCols: the candidates are bucketed by chunk (a counting sort into the
+// set's free record slice), each chunk's bottom and top per column come from
+// LDS atomics and are emitted in column order -- the x-sorted lower and upper
+// lists, written over consumed input -- and both chains are folded.
+constexpr uint32_t kLdsCols = 4096;
+constexpr uint32_t kLdsChunksMax = kColumns / kLdsCols;
+
+struct BigSmem {
+  union {
+    struct {
+      uint64_t bot[kLdsCols], top[kLdsCols];
+    } col;
+    WinSmem<kWin> win;
+  } u;
+  uint32_t start[kLdsChunksMax];  // first bucketed record of each chunk
+  uint32_t cur[kLdsChunksMax];    // scatter cursors (counts first)
+};
+
+// The hull of the c candidate records X[0..c) (set-local indices, columns
+// within [xmin, xmax]), using Y[0..c) as scratch; writes the counter-
+// clockwise hull to hull_out and returns h. Whole workgroup; X and Y are
+// overwritten.
+__device__ uint32_t big_set_hull(BigSmem& sm, Rec* X, Rec* Y, uint32_t c, int32_t xmin,
+                                 int32_t xmax, uint32_t* __restrict__ hull_out) {
+  const uint32_t nch = ((uint32_t)(xmax - xmin) / kLdsCols) + 1;
+  for (uint32_t k = threadIdx.x; k < nch; k += kBlock) sm.cur[k] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < c; i += kBlock)
+    atomicAdd(&sm.cur[(uint32_t)(X[i].x - xmin) / kLdsCols], 1u);
+  __syncthreads();
+  {
+    const uint32_t v = threadIdx.x < nch ? sm.cur[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t st = block_excl_scan(v, tot);
+    if (threadIdx.x < nch) { sm.start[threadIdx.x] = st; sm.cur[threadIdx.x] = st; }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
+    const Rec q = X[i];
+    const uint32_t p = atomicAdd(&sm.cur[(uint32_t)(q.x - xmin) / kLdsCols], 1u);
+    Y[p] = q;
+  }
+  __syncthreads();
+  constexpr uint32_t PER = kLdsCols / kBlock;
+  uint32_t nlo = 0, nup = 0;
+  for (uint32_t k = 0; k < nch; ++k) {
+    const uint32_t b0 = sm.start[k], b1 = k + 1 < nch ? sm.start[k + 1] : c;
+    if (b0 == b1) continue;
+    for (uint32_t i = threadIdx.x; i < kLdsCols; i += kBlock) {
+      sm.u.col.bot[i] = ~0ull;
+      sm.u.col.top[i] = 0ull;
+    }
+    __syncthreads();
+    const int32_t x0 = xmin + (int32_t)(k * kLdsCols);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+      const Rec q = Y[i];
+      const uint32_t cc = (uint32_t)(q.x - x0);
+      atomicMin(&sm.u.col.bot[cc], ((unsigned long long)(uint32_t)q.y << 32) | q.i);
+      atomicMax(&sm.u.col.top[cc],
+                ((unsigned long long)(uint32_t)(q.y + 1) << 32) | (0xFFFFFFFFu - q.i));
+    }
+    __syncthreads();
+    // Emission in column order: thread t owns columns [PER*t, PER*(t+1)).
+    uint32_t clo = 0, cup = 0;
+    for (uint32_t e = 0; e < PER; ++e) {
+      const uint32_t cc = threadIdx.x * PER + e;
+      const uint64_t b = sm.u.col.bot[cc];
+      if (b == ~0ull) continue;
+      const int32_t x = x0 + (int32_t)cc;
+      const bool two = (uint32_t)(sm.u.col.top[cc] >> 32) - 1 != (uint32_t)(b >> 32);
+      clo += 1 + ((x == xmax && two) ? 1 : 0);
+      cup += 1 + ((x == xmin && two) ? 1 : 0);
+    }
+    uint32_t tlo, tup;
+    uint32_t olo = nlo + block_excl_scan(clo, tlo);
+    uint32_t oup = nup + block_excl_scan(cup, tup);
+    for (uint32_t e = 0; e < PER; ++e) {
+      const uint32_t cc = threadIdx.x * PER + e;
+      const uint64_t b = sm.u.col.bot[cc];
+      if (b == ~0ull) continue;
+      const uint64_t t = sm.u.col.top[cc];
+      const uint32_t x = (uint32_t)(x0 + (int32_t)cc);
+      const bool two = (uint32_t)(t >> 32) - 1 != (uint32_t)(b >> 32);
+      Y[olo++] = bot_rec(x, b);
+      if ((int32_t)x == xmax && two) Y[olo++] = top_rec(x, t);
+      if ((int32_t)x == xmin && two) X[oup++] = bot_rec(x, b);
+      X[oup++] = top_rec(x, t);
+    }
+    nlo += tlo;
+    nup += tup;
+    __syncthreads();
+  }
+  const uint32_t nl = fold_chain<true>(sm.u.win, Y, nlo, Y);
+  for (uint32_t k = threadIdx.x; k < nl; k += kBlock) hull_out[k] = Y[k].i;
+  const uint32_t nu = fold_chain<false>(sm.u.win, X, nup, X);
+  for (uint32_t k = threadIdx.x; k + 2 < nu; k += kBlock) hull_out[nl + k] = X[nu - 2 - k].i;
+  return nl + (nu > 2 ? nu - 2 : 0);
 }
 
 // ------------------------------------------------------------- batch mode
 
 // Hull of every set whose candidates fit one block (<= T); a set still above
-// that waits for the next tile-hull round, or is reported as an overflow after
-// the last one (which runs with the larger block). Workgroups take sets with a
-// fixed stride.
+// that waits for the next tile-hull round (or, after the last one, for
+// k_batch_large). Workgroups take sets with a fixed stride.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_batch_final(const uint64_t* __restrict__ off,
                                                         uint32_t nsets,
@@ -1052,8 +1221,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_final(const uint64_t* __restri
                                                         SetState* __restrict__ sets, int stage,
                                                         const Rec* __restrict__ recs,
                                                         uint32_t* __restrict__ hull_idx,
-                                                        uint32_t* __restrict__ hull_count,
-                                                        int last) {
+                                                        uint32_t* __restrict__ hull_count) {
   __shared__ HullSmem<T> sm;
   const bool bad_off = bh->bad_offsets != 0;
   for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
@@ -1070,10 +1238,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_final(const uint64_t* __restri
       continue;
     }
     const uint32_t c = ss.cnt[stage];
-    if (c > (uint32_t)T) {
-      if (last && threadIdx.x == 0) { hull_count[s] = kCountOverflow; ss.done = 1; }
-      continue;
-    }
+    if (c > (uint32_t)T) continue;
     uint32_t nl, nu;
     const uint32_t h = tile_hull<T>(sm, recs + a, 0, c, nl, nu);
     for (uint32_t k = threadIdx.x; k < h; k += kBlock) hull_idx[a + k] = hull_elem(sm, k, nl, nu).i;
@@ -1132,6 +1297,33 @@ __global__ __launch_bounds__(kBlock) void k_batch_round(const uint64_t* __restri
   }
 }
 
+// Every set still unfinished after the rounds: its hull by big_set_hull,
+// one workgroup per set (sets with a fixed stride). The last round's output
+// (the candidates) is in `cand`; the set's slice of `spare` is free.
+__global__ __launch_bounds__(kBlock) void k_batch_large(const uint64_t* __restrict__ off,
+                                                        uint32_t nsets,
+                                                        const BatchHdr* __restrict__ bh,
+                                                        SetState* __restrict__ sets,
+                                                        Rec* __restrict__ cand,
+                                                        Rec* __restrict__ spare,
+                                                        uint32_t* __restrict__ hull_idx,
+                                                        uint32_t* __restrict__ hull_count) {
+  __shared__ BigSmem sm;
+  if (bh->bad_offsets) return;
+  for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
+    SetState& ss = sets[s];
+    if (ss.done) continue;
+    const uint32_t a = (uint32_t)off[s];
+    const uint32_t h = big_set_hull(sm, cand + a, spare + a, ss.cnt[kBatchRounds], ss.oct.vx[4],
+                                    ss.oct.vx[0], hull_idx + a);
+    if (threadIdx.x == 0) {
+      hull_count[s] = h;
+      ss.done = 1;
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- launchers
 
 hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result* res,
@@ -1165,28 +1357,29 @@ hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t ma
   return hipGetLastError();
 }
 
-uint32_t window_count(uint32_t c, uint32_t shift) {
-  if (c == 0) return 0;
-  return (c + shift + kWin - 1) / kWin;
-}
-
-hipError_t launch_window_round(const Rec* src_lo, const Rec* src_up, uint32_t cl, uint32_t cu,
-                               uint32_t shift, Rec* tmp_lo, Rec* tmp_up, uint32_t* wcnt_lo,
-                               uint32_t* wcnt_up, Rec* dst_lo, Rec* dst_up, Result* res,
-                               hipStream_t st) {
-  const uint32_t nwl = window_count(cl, shift), nwu = window_count(cu, shift);
-  if (nwl + nwu == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_window, dim3(nwl + nwu), dim3(kBlock), 0, st, src_lo, src_up, cl, cu, shift,
-                     nwl, tmp_lo, tmp_up, wcnt_lo, wcnt_up);
-  hipLaunchKernelGGL(k_window_pack, dim3(nwl + nwu), dim3(kBlock), 0, st, tmp_lo, tmp_up, shift,
-                     nwl, wcnt_lo, wcnt_up, dst_lo, dst_up, res, nwu);
-  return hipGetLastError();
-}
-
-hipError_t launch_large_final(const Rec* lo, const Rec* up, uint32_t cl, uint32_t cu, int single,
-                              Result* res, uint32_t* res_idx, hipStream_t st) {
-  hipLaunchKernelGGL(k_large_final, dim3(1), dim3(kBlock), 0, st, lo, up, cl, cu, single, res,
-                     res_idx);
+// The large-hull path from the records in[0..*in_count) (at most max_in)
+// to the hull in res_idx, with no host round trip: column table, the
+// x-sorted lower and upper lists, window chains, packing, one fold per list,
+// output. lstA / lstB hold two lists of kColumns + 2 records each (lower,
+// then upper); wcnt holds 2 * kWinPerList counts.
+hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
+                             uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
+                             uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
+                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st) {
+  const size_t cap = size_t(kColumns) + 2;
+  Rec* Alo = lstA;
+  Rec* Aup = lstA + cap;
+  Rec* Blo = lstB;
+  Rec* Bup = lstB + cap;
+  hipError_t e = launch_col_build(in, in_count, max_in, bot, top, colcnt, Alo, Aup, oct, res, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_window, dim3(2 * kWinPerList), dim3(kBlock), 0, st, Alo, Aup, res, Blo, Bup,
+                     wcnt);
+  hipLaunchKernelGGL(k_window_pack, dim3(2 * kWinPerList), dim3(kBlock), 0, st, Blo, Bup, wcnt, res,
+                     Alo, Aup);
+  hipLaunchKernelGGL(k_fold, dim3(2), dim3(kBlock), 0, st, Alo, Aup, res);
+  hipLaunchKernelGGL(k_large_out, dim3(1), dim3(kBlock), 0, st, Alo, Aup, res, res_idx, host,
+                     host_idx, host_n);
   return hipGetLastError();
 }
 
@@ -1200,7 +1393,7 @@ hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr*
                                   hipStream_t st) {
   Rec* buf[2] = {recA, recB};
   hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                     sets, 0, recA, hull_idx, hull_count, 0);
+                     sets, 0, recA, hull_idx, hull_count);
   for (int r = 0; r < kBatchRounds; ++r) {
     hipLaunchKernelGGL(k_batch_round_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, bh, sets, r,
                        rtiles);
@@ -1208,11 +1401,15 @@ hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr*
                        buf[r & 1], buf[(r + 1) & 1]);
     if (r + 1 < kBatchRounds)
       hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, 0);
+                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
     else
       hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, 1);
+                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
   }
+  // Sets whose candidates did not shrink to one workgroup: the last round
+  // wrote them to buf[kBatchRounds & 1].
+  hipLaunchKernelGGL(k_batch_large, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
+                     buf[kBatchRounds & 1], buf[(kBatchRounds + 1) & 1], hull_idx, hull_count);
   return hipGetLastError();
 }
 

@@ -69,8 +69,8 @@ struct Result {
   uint32_t pad;
   uint32_t round_cnt[kMaxRounds];   // records written by round r (index r+1 = output of round r)
   uint32_t round_tile[kMaxRounds];  // dynamic tile counter of round r
-  uint32_t win_cnt[4];              // window-round outputs (lower, upper) per parity
-  uint64_t tphase[12];              // shader-clock marks (builds with CH_PHASE_TIMING only)
+  uint32_t pack_cnt[2];             // large-hull path: window chains packed (lower, upper)
+  uint32_t fold_cnt[2];             // large-hull path: final chain lengths (lower, upper)
 };
 
 struct Rec {           // a candidate hull point: grid coordinates + index
@@ -163,7 +163,6 @@ constexpr uint32_t kBatchTile = 8192;     // default points per pass-1/pass-2 ti
 constexpr uint32_t kBatchTileMin = 4096;  // smallest tile the workspace is sized for
 constexpr uint32_t kBatchTileMax = 65536;
 constexpr int kBatchRounds = 4;           // tile-hull rounds for sets with many survivors
-constexpr uint32_t kCountOverflow = 0xFFFFFFFEu;
 constexpr uint32_t kCountInvalid = 0xFFFFFFFDu;
 
 struct SetTile {       // points [begin, end) of set `set` (global indices)

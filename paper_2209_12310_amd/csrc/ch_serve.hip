@@ -251,14 +251,6 @@ void run_batch(Slot& sl, std::vector<Request*>& b) {
     const uint32_t c = sl.pin_cnt[k];
     if (c == CH_COUNT_DOMAIN_ERROR) {
       r->status = CH_E_DOMAIN;
-    } else if (c == CH_COUNT_OVERFLOW) {
-      // Sets with many points in convex position: the general path.
-      r->hull.resize(std::max<uint32_t>(chk::hull_cap(r->n), 1));
-      uint32_t h = 0;
-      const ch_status cs = ch_hull(sl.ctx, d_xy + 2 * sl.pin_off[k], r->n, r->hull.data(),
-                                   (uint32_t)r->hull.size(), &h, d_ws, ws_bytes, st);
-      r->status = cs == CH_OK ? CH_OK : (cs == CH_E_DOMAIN ? CH_E_DOMAIN : CH_E_DEVICE);
-      r->hull.resize(cs == CH_OK ? h : 0);
     } else if (c > r->n) {
       r->status = CH_E_DEVICE;
     } else {

@@ -152,7 +152,7 @@ def test_domain_error_inside_polygon(ctx, where, kind):
 def test_batch_refined(ctx):
     _say("refined batch")
     import torch
-    cases = _cases(BATCH_SAMPLE_MIN, m=30)  # hulls below the batch's 4096-vertex block
+    cases = _cases(BATCH_SAMPLE_MIN)
     sets = list(cases.values()) + [workloads.annulus(BATCH_SAMPLE_MIN - 1, 88, 0.49, 0.5),
                                    workloads.annulus(BATCH_SAMPLE_MIN, 89, 0.49, 0.5)]
     off = np.zeros(len(sets) + 1, np.int64)
