@@ -19,10 +19,19 @@ paper (Keith, Ferrada, Navarro, arXiv 2209.12310) it follows:
 * ``heaphull``     -- the pipeline of Alg. 1 with the four queues merged into
                       one candidate set (the hull of the union is unique).
 * ``filter_parallel`` -- the divide-and-conquer CPU variant of Sec. III.
+* ``heaphull_queues`` -- Alg. 1, stages (2)-(4): the four queues built from
+                      Alg. 2's label array, a hull per queue, their union.
+* ``heaphull_parallel`` / ``chain_parallel`` -- the same on every host core
+                      (the CPU baseline of the measurements).
 
 Parity unpinned by the paper: the queue label rule (the paper gives no
 findQueue rule).  Everything else is pinned by the tests in
-``tests/test_oracle_*.py`` against brute force, closed forms and invariants.
+``tests/test_oracle.py`` against brute force, closed forms and invariants.
+
+``build()`` compiles a portable library (with the planted-mistake switch the
+tests use); ``native()`` compiles, on the host that runs it, an ``-O3
+-march=native`` copy with that switch compiled out, for timing the CPU
+baseline.  Both are the same source and arithmetic.
 """
 from __future__ import annotations
 
@@ -60,13 +69,7 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+def _bind(lib):
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
     lib.or_to_grid.argtypes = [P, I64, P, P]
@@ -84,8 +87,61 @@ def _load():
     lib.or_set_mutation.argtypes = [ctypes.c_int]
     lib.or_set_mutation.restype = None
     lib.or_max_threads.restype = ctypes.c_int
-    _lib = lib
+    lib.or_chain_parallel.argtypes = [P, P, I64, P, I64, P, ctypes.c_int]
+    lib.or_chain_parallel.restype = I64
+    lib.or_heaphull_queues.argtypes = [P, P, I64, P, P, P, P, ctypes.c_int]
+    lib.or_heaphull_queues.restype = I64
+    lib.or_heaphull_parallel.argtypes = [P, P, I64, P, ctypes.c_int]
+    lib.or_heaphull_parallel.restype = I64
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+_native = None
+
+
+def native():
+    """The oracle compiled on this host with ``-O3 -march=native`` and the
+    planted-mistake switch compiled out (a private temporary copy). Returns an
+    object with the same functions as this module's ``heaphull``,
+    ``heaphull_parallel`` and ``heaphull_queues``."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="oracle_native_")
+        path = os.path.join(d, "liboracle_native.so")
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-DOR_NO_MUTATION", "-std=c11",
+                               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", path, "-lm"])
+        _native = _Oracle(_bind(ctypes.CDLL(path)))
+    return _native
+
+
+class _Oracle:
+    """Entry points bound to one compiled copy of the oracle."""
+
+    def __init__(self, lib):
+        self.lib = lib
+
+    def heaphull(self, kx, ky):
+        return heaphull(kx, ky, lib=self.lib)
+
+    def heaphull_parallel(self, kx, ky, nthreads=0):
+        return heaphull_parallel(kx, ky, nthreads, lib=self.lib)
+
+    def heaphull_queues(self, kx, ky, labels, oct_idx=None, nthreads=1):
+        return heaphull_queues(kx, ky, labels, oct_idx, nthreads, lib=self.lib)
+
+    def max_threads(self):
+        return int(self.lib.or_max_threads())
 
 
 def _ptr(a: np.ndarray):
@@ -171,13 +227,57 @@ def chain(kx, ky, cand=None) -> np.ndarray:
     return hull[:h].copy()
 
 
-def heaphull(kx, ky) -> np.ndarray:
+def heaphull(kx, ky, lib=None) -> np.ndarray:
     """Alg. 1: extremes, octagon filter, chain over the survivors."""
     kx, ky = _k(kx, ky)
     n = kx.size
     surv = np.empty(max(n, 1), np.uint32)
     hull = np.empty(max(n, 1), np.uint32)
-    h = _load().or_heaphull(_ptr(kx), _ptr(ky), n, _ptr(surv), _ptr(hull))
+    h = (lib or _load()).or_heaphull(_ptr(kx), _ptr(ky), n, _ptr(surv), _ptr(hull))
+    return hull[:h].copy()
+
+
+def chain_parallel(kx, ky, cand=None, nthreads: int = 0) -> np.ndarray:
+    """``chain`` with the sort on ``nthreads`` threads (0: all)."""
+    kx, ky = _k(kx, ky)
+    n = kx.size
+    m = n if cand is None else len(cand)
+    hull = np.empty(max(m, 1), np.uint32)
+    if cand is None:
+        h = _load().or_chain_parallel(_ptr(kx), _ptr(ky), n, None, 0, _ptr(hull), int(nthreads))
+    else:
+        cand = np.ascontiguousarray(cand, np.uint32)
+        h = _load().or_chain_parallel(_ptr(kx), _ptr(ky), n, _ptr(cand), m, _ptr(hull), int(nthreads))
+    return hull[:h].copy()
+
+
+def heaphull_queues(kx, ky, labels, oct_idx=None, nthreads: int = 1, lib=None):
+    """Alg. 1, stages (2)-(4), from Alg. 2's label array: returns (hull,
+    queue sizes). ``oct_idx`` defaults to the octagon of ``extremes``."""
+    kx, ky = _k(kx, ky)
+    n = kx.size
+    if n == 0:
+        return np.empty(0, np.uint32), np.zeros(4, np.int64)
+    if oct_idx is None:
+        oct_idx = extremes(kx, ky)
+    oct_idx = np.ascontiguousarray(oct_idx, np.int64)
+    labels = np.ascontiguousarray(labels, np.uint8)
+    if labels.size != n:
+        raise ValueError("one label per point")
+    hull = np.empty(n + 4, np.uint32)
+    qc = np.zeros(4, np.int64)
+    h = (lib or _load()).or_heaphull_queues(_ptr(kx), _ptr(ky), n, _ptr(oct_idx), _ptr(labels),
+                                            _ptr(hull), _ptr(qc), int(nthreads))
+    return hull[:h].copy(), qc
+
+
+def heaphull_parallel(kx, ky, nthreads: int = 0, lib=None) -> np.ndarray:
+    """The full heaphull on ``nthreads`` host threads (0: all): parallel
+    extremes and filter, labels, four queues, each hulled in parallel."""
+    kx, ky = _k(kx, ky)
+    n = kx.size
+    hull = np.empty(max(n, 1), np.uint32)
+    h = (lib or _load()).or_heaphull_parallel(_ptr(kx), _ptr(ky), n, _ptr(hull), int(nthreads))
     return hull[:h].copy()
 
 

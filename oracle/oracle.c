@@ -45,10 +45,17 @@
 #endif
 
 /* Planted-mistake switch used only by the test that shows the pins bite.
- * 0 = the oracle as written. Any other value injects one known mistake. */
+ * 0 = the oracle as written. Any other value injects one known mistake.
+ * The timed CPU-baseline build (OR_NO_MUTATION) compiles the switch out. */
+#ifdef OR_NO_MUTATION
+#define g_mutation 0
+void or_set_mutation(int m) { (void)m; }
+int or_get_mutation(void) { return 0; }
+#else
 static int g_mutation = 0;
 void or_set_mutation(int m) { g_mutation = m; }
 int or_get_mutation(void) { return g_mutation; }
+#endif
 
 int or_version(void) { return 1; }
 
@@ -296,23 +303,13 @@ static int rec_cmp(const void* a, const void* b) {
   return 0;
 }
 
-/* Andrew's monotone chain over a candidate subset of the points.
- * cand == NULL means all n points; otherwise cand[0..m) lists point indices.
- * hull receives at most (m) indices, counter-clockwise from the
- * lexicographic minimum; returns h. Steps: sort by (kx, ky, index); keep the
+/* Andrew's scan over records already sorted by (kx, ky, index): keep the
  * first of each run of equal coordinates (the smallest index); lower chain
  * left to right and upper chain right to left, each popping while the last
- * turn is not strictly counter-clockwise. */
-int64_t or_chain(const int32_t* kx, const int32_t* ky, int64_t n,
-                 const uint32_t* cand, int64_t m, uint32_t* hull) {
-  if (!cand) m = n;
-  if (m <= 0) return 0;
-  rec_t* r = (rec_t*)malloc(sizeof(rec_t) * (size_t)m);
-  for (int64_t t = 0; t < m; ++t) {
-    uint32_t j = cand ? cand[t] : (uint32_t)t;
-    r[t].x = kx[j]; r[t].y = ky[j]; r[t].i = j;
-  }
-  qsort(r, (size_t)m, sizeof(rec_t), rec_cmp);
+ * turn is not strictly counter-clockwise. r is compacted in place; hull
+ * receives the counter-clockwise hull from the lexicographic minimum.
+ * Returns h (m >= 1). */
+static int64_t chain_sorted(rec_t* r, int64_t m, uint32_t* hull) {
   int64_t u = 0;
   for (int64_t t = 0; t < m; ++t) {
     if (u > 0 && r[u - 1].x == r[t].x && r[u - 1].y == r[t].y) {
@@ -321,7 +318,7 @@ int64_t or_chain(const int32_t* kx, const int32_t* ky, int64_t n,
     }
     r[u++] = r[t];
   }
-  if (u == 1) { hull[0] = r[0].i; free(r); return 1; }
+  if (u == 1) { hull[0] = r[0].i; return 1; }
   rec_t** st = (rec_t**)malloc(sizeof(rec_t*) * (size_t)(2 * u + 1));
   int64_t k = 0;
   for (int64_t t = 0; t < u; ++t) { /* lower chain */
@@ -345,7 +342,185 @@ int64_t or_chain(const int32_t* kx, const int32_t* ky, int64_t n,
     for (int64_t a = 1, b = h - 1; a < b; ++a, --b) { uint32_t x = hull[a]; hull[a] = hull[b]; hull[b] = x; }
   }
   free(st);
+  return h;
+}
+
+static rec_t* gather_recs(const int32_t* kx, const int32_t* ky, const uint32_t* cand, int64_t m) {
+  rec_t* r = (rec_t*)malloc(sizeof(rec_t) * (size_t)m);
+  for (int64_t t = 0; t < m; ++t) {
+    uint32_t j = cand ? cand[t] : (uint32_t)t;
+    r[t].x = kx[j]; r[t].y = ky[j]; r[t].i = j;
+  }
+  return r;
+}
+
+/* Andrew's monotone chain over a candidate subset of the points.
+ * cand == NULL means all n points; otherwise cand[0..m) lists point indices.
+ * hull receives at most (m) indices, counter-clockwise from the
+ * lexicographic minimum; returns h. Steps: sort by (kx, ky, index), then the
+ * scan of chain_sorted. */
+int64_t or_chain(const int32_t* kx, const int32_t* ky, int64_t n,
+                 const uint32_t* cand, int64_t m, uint32_t* hull) {
+  if (!cand) m = n;
+  if (m <= 0) return 0;
+  rec_t* r = gather_recs(kx, ky, cand, m);
+  qsort(r, (size_t)m, sizeof(rec_t), rec_cmp);
+  int64_t h = chain_sorted(r, m, hull);
   free(r);
+  return h;
+}
+
+/* Multi-core sort for the CPU baseline: each thread sorts one contiguous
+ * chunk with qsort, then neighbouring sorted runs are merged pairwise (the
+ * merges of a round in parallel) until one run is left. Same order as one
+ * qsort: the (kx, ky, index) keys are distinct. */
+static void sort_recs_parallel(rec_t* r, int64_t m, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads <= 1 || m < 4096) {
+    qsort(r, (size_t)m, sizeof(rec_t), rec_cmp);
+    return;
+  }
+  int64_t* b = (int64_t*)malloc(sizeof(int64_t) * ((size_t)nthreads + 1));
+  for (int t = 0; t <= nthreads; ++t) b[t] = m * t / nthreads;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+  for (int t = 0; t < nthreads; ++t)
+    qsort(r + b[t], (size_t)(b[t + 1] - b[t]), sizeof(rec_t), rec_cmp);
+  rec_t* tmp = (rec_t*)malloc(sizeof(rec_t) * (size_t)m);
+  for (int w = 1; w < nthreads; w *= 2) {
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int t = 0; t < nthreads; t += 2 * w) {
+      if (t + w >= nthreads) continue;
+      const int64_t lo = b[t], mid = b[t + w], hi = b[t + 2 * w < nthreads ? t + 2 * w : nthreads];
+      int64_t i = lo, j = mid, o = lo;
+      while (i < mid && j < hi) tmp[o++] = rec_cmp(&r[j], &r[i]) < 0 ? r[j++] : r[i++];
+      while (i < mid) tmp[o++] = r[i++];
+      while (j < hi) tmp[o++] = r[j++];
+      memcpy(r + lo, tmp + lo, sizeof(rec_t) * (size_t)(hi - lo));
+    }
+  }
+  free(tmp);
+  free(b);
+#else
+  (void)nthreads;
+  qsort(r, (size_t)m, sizeof(rec_t), rec_cmp);
+#endif
+}
+
+/* or_chain on nthreads threads (the sort in parallel, then the scan). */
+int64_t or_chain_parallel(const int32_t* kx, const int32_t* ky, int64_t n,
+                          const uint32_t* cand, int64_t m, uint32_t* hull, int nthreads) {
+  if (!cand) m = n;
+  if (m <= 0) return 0;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#endif
+  rec_t* r = gather_recs(kx, ky, cand, m);
+  sort_recs_parallel(r, m, nthreads);
+  int64_t h = chain_sorted(r, m, hull);
+  free(r);
+  return h;
+}
+
+/* ------------------------------------------------------- the four queues */
+
+/* Alg. 1, stages (2)-(4): the surviving points go to four queues by their
+ * label (Alg. 2's array Q: 0 for a discarded point, else the queue), each
+ * queue gets its own hull, and the hull of the set is the union of the
+ * pieces. Queue q (1..4) holds the quadrant between the axis extremes
+ * A_q and A_{q+1} (A = E, N, W, S, then E again: octagon slots 0, 2, 4, 6);
+ * its piece is the counter-clockwise arc from A_q to A_{q+1} of the hull of
+ * the queue's points together with A_q and A_{q+1} (an axis extreme that
+ * coincides with a corner vertex carries that corner's label, so it may sit
+ * in the neighbouring queue).
+ * Each axis extreme, with the tie-breaks of the extremes, is a strict
+ * vertex of every subset containing it, so the arcs meet at them; the union
+ * starts at the lexicographic minimum (W).
+ * oct: the octagon's point indices in slot order; labels: n bytes; qcount
+ * (may be NULL) receives the queue sizes. The queue hulls run one after the
+ * other, each on nthreads threads. Returns h. */
+int64_t or_heaphull_queues(const int32_t* kx, const int32_t* ky, int64_t n,
+                           const int64_t oct[8], const uint8_t* labels, uint32_t* hull,
+                           int64_t qcount[4], int nthreads) {
+  if (n <= 0) return 0;
+  /* Queue build: one pass over the labels, indices in ascending order. */
+  int64_t cnt[5] = {0, 0, 0, 0, 0};
+  for (int64_t j = 0; j < n; ++j) cnt[labels[j] <= 4 ? labels[j] : 0]++;
+  uint32_t* q[5];
+  for (int k = 1; k <= 4; ++k) q[k] = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(cnt[k] + 2));
+  int64_t fill[5] = {0, 0, 0, 0, 0};
+  for (int64_t j = 0; j < n; ++j) {
+    const int k = labels[j];
+    if (k >= 1 && k <= 4) q[k][fill[k]++] = (uint32_t)j;
+  }
+  if (qcount)
+    for (int k = 0; k < 4; ++k) qcount[k] = cnt[k + 1];
+  /* The axis extremes, each by its smallest index. */
+  uint32_t ax[5];
+  for (int k = 0; k < 4; ++k) {
+    const int64_t v = oct[2 * k];
+    int64_t best = v;
+    for (int64_t j = 0; j < v; ++j)
+      if (kx[j] == kx[v] && ky[j] == ky[v]) { best = j; break; }
+    ax[k] = (uint32_t)best;
+  }
+  ax[4] = ax[0];
+  /* Per-queue hulls and their arcs. */
+  uint32_t* out = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n + 4));
+  int64_t h = 0;
+  for (int k = 1; k <= 4; ++k) {
+    const uint32_t a = ax[k - 1], b = ax[k];
+    const int64_t m = cnt[k];
+    q[k][m] = a; /* the arc's end points join the queue */
+    q[k][m + 1] = g_mutation == 9 ? a : b; /* 9 (planted): A_{q+1} left out */
+    uint32_t* hk = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m + 2));
+    const int64_t hq = nthreads > 1 ? or_chain_parallel(kx, ky, n, q[k], m + 2, hk, nthreads)
+                                    : or_chain(kx, ky, n, q[k], m + 2, hk);
+    int64_t pa = -1, pb = -1;
+    for (int64_t t = 0; t < hq; ++t) {
+      if (kx[hk[t]] == kx[a] && ky[hk[t]] == ky[a]) pa = t;
+      if (kx[hk[t]] == kx[b] && ky[hk[t]] == ky[b]) pb = t;
+    }
+    /* The arc from A_q up to (not including) A_{q+1}: the next arc starts
+     * there. pa and pb always exist (extremes of the queue's hull). */
+    if (pa >= 0 && pb >= 0)
+      for (int64_t t = pa; t != pb; t = (t + 1) % hq) out[h++] = hk[t];
+    free(hk);
+  }
+  if (h == 0) { /* every axis extreme is the same point */
+    out[h++] = ax[0];
+  }
+  /* Start at the lexicographic minimum, the west extreme. */
+  int64_t s = 0;
+  for (int64_t t = 0; t < h; ++t)
+    if (kx[out[t]] == kx[ax[2]] && ky[out[t]] == ky[ax[2]]) { s = t; break; }
+  for (int64_t t = 0; t < h; ++t) hull[t] = out[(s + t) % h];
+  free(out);
+  for (int k = 1; k <= 4; ++k) free(q[k]);
+  return h;
+}
+
+/* The full heaphull on the CPU's cores (the paper's divide-and-conquer
+ * variant, Sec. III): chunked extremes and filter per thread, the labels of
+ * the survivors, then the four queues, each hulled on every thread. */
+int64_t or_heaphull_parallel(const int32_t* kx, const int32_t* ky, int64_t n, uint32_t* hull,
+                             int nthreads) {
+  if (n <= 0) return 0;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+  nthreads = 1;
+#endif
+  int64_t oct[8];
+  uint32_t* surv = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+  const int64_t m = or_filter_parallel(kx, ky, n, oct, surv, nthreads);
+  uint8_t* labels = (uint8_t*)calloc((size_t)n, 1);
+  int64_t vx[8], vy[8];
+  load_octagon(kx, ky, oct, vx, vy);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+  for (int64_t t = 0; t < m; ++t) labels[surv[t]] = (uint8_t)classify(kx[surv[t]], ky[surv[t]], vx, vy);
+  const int64_t h = or_heaphull_queues(kx, ky, n, oct, labels, hull, NULL, nthreads);
+  free(labels);
+  free(surv);
   return h;
 }
 

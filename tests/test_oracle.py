@@ -299,6 +299,86 @@ def test_heaphull_equals_plain_chain(name):
     assert np.array_equal(oracle.heaphull(kx, ky), oracle.chain(kx, ky))
 
 
+# ------------------------------------------- the four queues of Alg. 1
+
+def _queues(pts):
+    kx = np.array([p[0] for p in pts], np.int32)
+    ky = np.array([p[1] for p in pts], np.int32)
+    _, lab = oracle.filter(kx, ky)
+    return kx, ky, lab
+
+
+def test_queue_heaphull_matches_brute_force():
+    """Alg. 1 with its four queues (a hull per queue, then the union) gives
+    the brute-force hull on small sets full of duplicates, collinear runs and
+    coinciding extremes."""
+    rng = np.random.default_rng(31)
+    for trial in range(400):
+        n = int(rng.integers(1, 45))
+        pts = _rand_small(rng, n, int(rng.integers(1, 10)))
+        kx, ky, lab = _queues(pts)
+        got, qc = oracle.heaphull_queues(kx, ky, lab)
+        assert got.tolist() == brute.hull_brute(pts), (trial, pts)
+        assert qc.tolist() == [int((lab == q).sum()) for q in (1, 2, 3, 4)]
+
+
+@pytest.mark.parametrize("case", ["grid", "circle", "parabola", "collinear", "identical", "two",
+                                  "square_sides", "diagonal", "vertical"])
+def test_queue_heaphull_closed_cases(case):
+    c = 1 << 19
+    pts = {
+        "grid": [(x, y) for x in range(20) for y in range(20)],
+        "circle": [(c + x, c + y) for x, y in _lattice_circle(5 * 13 * 17 * 29)],
+        "parabola": [(i, i * i) for i in range(1024)],
+        "collinear": [(x, 2 * x + 3) for x in (5, 1, 9, 9, 1, 4, 7)],
+        "identical": [(7, 7)] * 9,
+        "two": [(1, 2), (3, 4), (1, 2)],
+        "square_sides": [(x, 0) for x in range(0, 101, 10)] + [(100, y) for y in range(0, 101, 5)]
+        + [(x, 100) for x in range(0, 101, 4)] + [(0, y) for y in range(0, 101, 20)],
+        "diagonal": [(x, x) for x in range(50)],
+        "vertical": [(9, y) for y in range(40)],
+    }[case]
+    perm = np.random.default_rng(32).permutation(len(pts))
+    pts = [pts[i] for i in perm]
+    kx, ky, lab = _queues(pts)
+    got, _ = oracle.heaphull_queues(kx, ky, lab)
+    assert got.tolist() == oracle.heaphull(kx, ky).tolist()
+    if len(pts) <= 60:
+        assert got.tolist() == brute.hull_brute(pts)
+
+
+@pytest.mark.parametrize("name", golden_names())
+def test_queue_heaphull_golden(name):
+    g = load_golden(name)
+    kx, ky = oracle.to_grid(grid_to_xy(g["points"]))
+    got, _ = oracle.heaphull_queues(kx, ky, np.asarray(g["labels"], np.uint8))
+    assert got.tolist() == g["hull"]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "normal", "annulus"])
+def test_parallel_heaphull_equals_sequential(kind):
+    xy = workloads.by_kind(kind, 300_000, 33)
+    kx, ky = oracle.to_grid(xy)
+    want = oracle.heaphull(kx, ky)
+    _, lab = oracle.filter(kx, ky)
+    for t in (1, 3, 8):
+        assert np.array_equal(oracle.heaphull_parallel(kx, ky, t), want), t
+        assert np.array_equal(oracle.chain_parallel(kx, ky, None, t), want), t
+        assert np.array_equal(oracle.heaphull_queues(kx, ky, lab, None, t)[0], want), t
+
+
+def test_native_build_matches():
+    """The -O3 -march=native copy timed as the CPU baseline computes the same
+    hulls (same source, planted-mistake switch compiled out)."""
+    nat = oracle.native()
+    for kind in ("uniform", "annulus"):
+        xy = workloads.by_kind(kind, 100_000, 34)
+        kx, ky = oracle.to_grid(xy)
+        want = oracle.heaphull(kx, ky)
+        assert np.array_equal(nat.heaphull(kx, ky), want)
+        assert np.array_equal(nat.heaphull_parallel(kx, ky), want)
+
+
 # ----------------------------------------------------- planted mistakes bite
 
 def _battery() -> list[str]:
@@ -322,6 +402,10 @@ def _battery() -> list[str]:
         if oracle.heaphull(kx, ky).tolist() != brute.hull_brute(pts):
             failed.append("brute_hull")
             break
+        _, lab = oracle.filter(kx, ky)
+        if oracle.heaphull_queues(kx, ky, lab)[0].tolist() != brute.hull_brute(pts):
+            failed.append("queue_hull")
+            break
         idx = oracle.extremes(kx, ky)
         if [pts[i] for i in idx] != brute.extremes_keys(pts):
             failed.append("extremes_keys")
@@ -339,7 +423,7 @@ def test_battery_passes_unmutated():
     assert _battery() == []
 
 
-@pytest.mark.parametrize("mutation", range(1, 9))
+@pytest.mark.parametrize("mutation", range(1, 10))
 def test_planted_mistake_is_caught(mutation):
     try:
         oracle.set_mutation(mutation)
