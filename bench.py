@@ -83,36 +83,140 @@ def load_traffic(n: int, kernel: str):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(xy, budget_s: float = 8.0):
-    """The CPU oracle as it stands, timed on the host: the multi-core variant
-    (grid conversion, the OpenMP divide-and-conquer octagon filter on every
-    host thread, monotone chain of the survivors) and the single-thread
-    heaphull, each on the full headline input within a time budget."""
+def cpu_baseline(xy, t, ctx, budget_s: float = 6.0):
+    """The CPU oracle as it stands, built on this host with -O3 -march=native
+    (the planted-mistake switch compiled out), timed on the full headline
+    input within a time budget per variant:
+      value            the multi-core heaphull of Sec. III taken to the end:
+                       grid conversion, then extremes and filter by divide and
+                       conquer, labels, the four queues, each hulled with a
+                       parallel sort, on every host thread;
+      single_thread    the sequential heaphull (extremes, filter, chain);
+      paper_architecture  the paper's own split (Sec. III): the label array
+                       of Alg. 2 on this GPU (ch_gpufilter with the two-kernel
+                       extreme search), copied to pinned host memory, then the
+                       four queues and their hulls on the host cores.
+    Each variant's hull is checked against ch_hull's."""
+    import numpy as np
+    import torch
+
     import oracle
+    nat = oracle.native()
+    n = xy.shape[0]
+    want = ctx.hull(t)
 
     def timed(fn):
-        reps, total = 0, 0.0
+        reps, total, out = 0, 0.0, None
         while reps < 5 and (reps == 0 or total < budget_s):
             t0 = time.perf_counter()
-            fn()
+            out = fn()
             total += time.perf_counter() - t0
             reps += 1
-        return reps, total
+        return reps, total, out
 
-    def multi():
-        kx, ky = oracle.to_grid(xy)
-        _, surv = oracle.filter_parallel(kx, ky)
-        return oracle.chain(kx, ky, surv)
+    cores = nat.max_threads()
+    t0 = time.perf_counter()
+    kx, ky = oracle.to_grid(xy)
+    grid_s = time.perf_counter() - t0
+    reps, total, h = timed(lambda: nat.heaphull_parallel(kx, ky, 0))
+    assert np.array_equal(h, want), "multi-core heaphull differs from ch_hull"
+    multi_s = grid_s + total / reps
+    reps1, total1, h1 = timed(lambda: nat.heaphull(kx, ky))
+    assert np.array_equal(h1, want), "sequential heaphull differs from ch_hull"
+    single_s = grid_s + total1 / reps1
 
-    n = xy.shape[0]
-    cores = oracle.max_threads()
-    reps, total = timed(multi)
-    reps1, total1 = timed(lambda: oracle.hull(xy))
-    return {"value": round(n * reps / total / 1e6, 3), "unit": "Mpts/s", "cores": cores, "kind": "oracle",
-            "sample": f"full {WORKLOAD} input ({n} points), {reps} run(s) in {total:.1f} s: grid "
-                      f"conversion, octagon filter on {cores} threads (divide and conquer), monotone chain",
-            "single_thread_value": round(n * reps1 / total1 / 1e6, 3),
-            "single_thread_sample": f"{reps1} run(s) in {total1:.1f} s of the sequential heaphull"}
+    # The paper's architecture: GPU labels -> host -> CPU queues and hulls.
+    lab_dev = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    oct_dev = torch.empty(24, dtype=torch.int32, device="cuda:0")
+    lab_host = torch.empty(n, dtype=torch.uint8).pin_memory()
+    oct_host = torch.empty(24, dtype=torch.int32).pin_memory()
+
+    def paper():
+        a = time.perf_counter()
+        ctx.gpufilter_async(t, lab_dev, oct_dev, None, "two_kernels")
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        lab_host.copy_(lab_dev, non_blocking=True)
+        oct_host.copy_(oct_dev, non_blocking=True)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        labels = lab_host.numpy()
+        oct_idx = oct_host.numpy()[16:24].view(np.uint32).astype(np.int64)
+        hull, _ = nat.heaphull_queues(kx, ky, labels, oct_idx, cores)
+        d = time.perf_counter()
+        return hull, (b - a, c - b, d - c)
+
+    paper()  # warm the GPU path
+    times = []
+    for _ in range(3):
+        hp, parts = paper()
+        times.append(parts)
+    assert np.array_equal(hp, want), "paper architecture differs from ch_hull"
+    gpu_s, d2h_s, cpu_s = (float(np.median([p[i] for p in times])) for i in range(3))
+    return {"value": round(n / multi_s / 1e6, 3), "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"full {WORKLOAD} input ({n} points): grid conversion ({grid_s:.2f} s, one "
+                      f"thread), then the four-queue heaphull on {cores} threads, {reps} run(s) in "
+                      f"{total:.1f} s; oracle built -O3 -march=native",
+            "ms": round(multi_s * 1e3, 1),
+            "single_thread_value": round(n / single_s / 1e6, 3),
+            "single_thread_sample": f"grid conversion, then {reps1} run(s) in {total1:.1f} s of the "
+                                    f"sequential heaphull",
+            "paper_architecture": {
+                "value": round(n / (gpu_s + d2h_s + cpu_s) / 1e6, 3), "unit": "Mpts/s",
+                "ms": round((gpu_s + d2h_s + cpu_s) * 1e3, 2),
+                "gpu_labels_ms": round(gpu_s * 1e3, 3), "d2h_labels_ms": round(d2h_s * 1e3, 3),
+                "cpu_queues_hull_ms": round(cpu_s * 1e3, 2), "cores": cores,
+                "what": "ch_gpufilter (two-kernel extremes, Alg. 2 labels) on the GPU, labels and "
+                        "octagon copied to pinned host memory, four queues + hulls on the host "
+                        "(kx, ky already on the host); median of 3"}}
+
+
+def bench_paper_pipeline(ctx, t, steps: int) -> dict:
+    """Alg. 1 stage by stage on the device (ch_hull_queues) with each extreme
+    search, and the A/B of the extreme searches alone: Sec. III's two
+    reductions (axis extremes, then Manhattan corners) against the one-read
+    search, from the library's kernel events."""
+    import torch
+    n = t.shape[0]
+    out = {}
+    ref = ctx.hull(t)
+    for mode in ("two_kernels", "fused"):
+        for _ in range(2):
+            got, qc = ctx.hull_queues(t, extremes=mode)
+        assert (got == ref).all(), f"ch_hull_queues ({mode}) differs from ch_hull"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.hull_queues(t, extremes=mode)
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(steps):
+            ctx.hull_queues(t, extremes=mode)
+        ctx.profile_enable(False)
+        st = ctx.profile_read()
+        out[f"hull_queues_{mode}"] = {
+            "ms_per_step": round(ms, 4), "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+            "queue_sizes": [int(v) for v in qc],
+            "kernels_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in st.items() if v[0]}}
+    lab = torch.empty(n, dtype=torch.uint8, device=t.device)
+    ab = {}
+    for mode in ("two_kernels", "fused"):
+        ctx.gpufilter_async(t, lab, None, None, mode)
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(steps):
+            ctx.gpufilter_async(t, lab, None, None, mode)
+        ctx.profile_enable(False)
+        st = ctx.profile_read()
+        k = {name: round(v[1] / v[0] * 1e3, 2) for name, v in st.items() if v[0]}
+        ext = ("axis_extremes", "corner_extremes") if mode == "two_kernels" else ("reduce8",)
+        ab[mode] = {"extremes_us": round(sum(k.get(e, 0.0) for e in ext), 2),
+                    "gpufilter_us": round(sum(k.values()), 2), "kernels_us": k,
+                    "extremes_read_bytes": (16 if mode == "two_kernels" else 8) * n}
+    ab["speedup_extremes"] = round(ab["two_kernels"]["extremes_us"] / ab["fused"]["extremes_us"], 3)
+    out["extremes_ab"] = ab
+    return out
 
 
 def measure_read_stream(ctx, buf, reps: int = 10) -> dict:
@@ -346,6 +450,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the other single-set configurations")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-pipeline measurements")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -458,6 +563,9 @@ def main() -> int:
         "read_stream": read_stream,
         "kernels": kernels,
     }
+    if not args.no_paper:
+        log("paper pipeline: ch_hull_queues and the extreme-search A/B")
+        out["paper_pipeline"] = bench_paper_pipeline(ctx, t, max(3, min(args.steps, 10)))
     del t
     torch.cuda.synchronize()
     out["single_sets"] = {WORKLOAD: {"workload": WORKLOAD, "n": n, "ms_per_step": round(ms, 4),
@@ -476,8 +584,11 @@ def main() -> int:
     if not args.no_serve:
         out["serve"] = bench_serve(ctx)
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(xy)
+        log("cpu baseline (oracle) and the paper's architecture")
+        t = torch.from_numpy(xy).to(dev)
+        out["cpu_baseline"] = cpu_baseline(xy, t, ctx)
+        del t
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0

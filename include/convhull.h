@@ -150,6 +150,58 @@ typedef struct {
 } ch_hull_info;
 ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out);
 
+/*
+ * The extreme search of Alg. 1/2 (findExtremes) comes in two forms:
+ *   CH_EXTREMES_TWO_KERNELS  as Sec. III runs it on the GPU: one reduction for
+ *                            the four axis extremes, then a second one for the
+ *                            point of least Manhattan distance to each corner
+ *                            of the box they span (it needs the first result);
+ *                            the points are read twice.
+ *   CH_EXTREMES_FUSED        all eight in one read: for a point inside that box
+ *                            the Manhattan distance to a corner is a constant
+ *                            minus +-x +-y, so no second pass is needed.
+ * Both give the same octagon (with the tie-breaks of ch_octagon).
+ */
+#define CH_EXTREMES_FUSED 0
+#define CH_EXTREMES_TWO_KERNELS 1
+
+/* Device workspace bytes needed by ch_gpufilter / ch_hull_queues for n points. */
+size_t ch_gpufilter_workspace_bytes(uint32_t n);
+size_t ch_hull_queues_workspace_bytes(uint32_t n);
+
+/*
+ * ch_gpufilter -- Alg. 2 (GPUfilter): findExtremes (extremes_mode), then the
+ * queue label of every point, the array Q the paper copies back to the host
+ * to build its four queues (Sec. III). Asynchronous like ch_filter.
+ *   d_label   n bytes: 0 for a discarded point, else its queue 1..4 (the rule
+ *             of ch_filter's d_label).
+ *   d_oct     optional (NULL to skip): the octagon.
+ *   d_count   optional (NULL to skip): the number of surviving points, or
+ *             CH_COUNT_DOMAIN_ERROR (the labels are then unspecified).
+ *   d_ws      workspace of ws_bytes >= ch_gpufilter_workspace_bytes(n).
+ * Errors as ch_filter; CH_E_INVALID_ARG also for an unknown extremes_mode.
+ */
+ch_status ch_gpufilter(ch_ctx* ctx, const float* d_xy, uint32_t n, int extremes_mode,
+                       uint8_t* d_label, ch_octagon* d_oct, uint32_t* d_count, void* d_ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * ch_hull_queues -- Alg. 1 stage by stage, all on the device: (1) findExtremes
+ * (extremes_mode) and the octagon; (2) the octagon filter with the label
+ * array of Alg. 2, and the four queues Q_1..Q_4 built from it (each in
+ * ascending index order); (3) a partial order per queue: its points bucketed
+ * by grid column (only the top point of a column can lie on the upper arcs
+ * fed by Q_1 and Q_2, only the bottom one on the lower arcs of Q_3 and Q_4);
+ * (4) the hull of each queue -- the counter-clockwise arc between its two
+ * axis extremes (Q_1: E to N, Q_2: N to W, Q_3: W to S, Q_4: S to E) -- and
+ * their union. Synchronous like ch_hull, with the same result and errors.
+ *   h_qcount  optional (NULL to skip): 4 uint32, the queue sizes n_1..n_4.
+ *   d_ws      workspace of ws_bytes >= ch_hull_queues_workspace_bytes(n).
+ */
+ch_status ch_hull_queues(ch_ctx* ctx, const float* d_xy, uint32_t n, int extremes_mode,
+                         uint32_t* h_hull_idx, uint32_t cap, uint32_t* h_out, uint32_t* h_qcount,
+                         void* d_ws, size_t ws_bytes, void* stream);
+
 /* Count value ch_hull_batch writes for every set when the offsets are not
  * non-decreasing from 0 to total_points (a set with a domain error gets
  * CH_COUNT_DOMAIN_ERROR, above). Every other set gets its hull, whatever its

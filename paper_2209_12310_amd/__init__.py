@@ -166,6 +166,66 @@ class Context:
             self._raise(st)
         return out[: h.value].copy()
 
+    @staticmethod
+    def _extremes_mode(extremes: str) -> int:
+        modes = {"fused": _capi.CH_EXTREMES_FUSED, "two_kernels": _capi.CH_EXTREMES_TWO_KERNELS}
+        if extremes not in modes:
+            raise ValueError(f"extremes must be one of {sorted(modes)}")
+        return modes[extremes]
+
+    def gpufilter_async(self, xy, labels, octagon_dev=None, count=None, extremes: str = "two_kernels"):
+        """ch_gpufilter (Alg. 2) on caller-provided device buffers: labels
+        (n,) uint8, optional octagon (24,) int32 and count (1,) int32;
+        enqueues on the current stream and returns immediately."""
+        n = _check_points(xy)
+        mode = self._extremes_mode(extremes)
+        ws = self.workspace(self._lib.ch_gpufilter_workspace_bytes(n))
+        st = self._lib.ch_gpufilter(
+            self._h, ctypes.c_void_p(xy.data_ptr()), n, mode, ctypes.c_void_p(labels.data_ptr()),
+            ctypes.c_void_p(octagon_dev.data_ptr()) if octagon_dev is not None else None,
+            ctypes.c_void_p(count.data_ptr()) if count is not None else None,
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+
+    def gpufilter(self, xy, extremes: str = "two_kernels"):
+        """Alg. 2: (labels as a device uint8 tensor, octagon dict, survivor
+        count)."""
+        torch = _torch()
+        n = _check_points(xy)
+        dev = xy.device
+        lab = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+        octd = torch.empty(24, dtype=torch.int32, device=dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=dev)
+        self.gpufilter_async(xy, lab, octd, cnt, extremes)
+        c = int(cnt.cpu().numpy().view(np.uint32)[0])
+        if c == CH_COUNT_DOMAIN_ERROR:
+            raise DomainError(_capi.CH_E_DOMAIN, "input outside the 2^-20 grid on [0,1)")
+        oct_np = None
+        if n:
+            o = octd.cpu().numpy()
+            oct_np = {"kx": o[0:8].copy(), "ky": o[8:16].copy(), "idx": o[16:24].view(np.uint32).copy()}
+        return lab[:n], oct_np, c
+
+    def hull_queues(self, xy, extremes: str = "fused", cap: int | None = None):
+        """ch_hull_queues (Alg. 1 with its four queues): returns (hull
+        indices, queue sizes) as numpy uint32 arrays."""
+        n = _check_points(xy)
+        mode = self._extremes_mode(extremes)
+        ws = self.workspace(self._lib.ch_hull_queues_workspace_bytes(n))
+        if cap is None:
+            cap = max(min(n, 1 << 21), 1)
+        out = np.empty(cap, np.uint32)
+        qc = np.zeros(4, np.uint32)
+        h = ctypes.c_uint32(0)
+        st = self._lib.ch_hull_queues(self._h, ctypes.c_void_p(xy.data_ptr()), n, mode,
+                                      out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(h),
+                                      qc.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel(), self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+        return out[: h.value].copy(), qc
+
     def read_stream_async(self, buf, blocks: int = 0):
         """ch_diag_read_stream over a contiguous device tensor (its bytes,
         rounded down to a multiple of 16), on the current stream."""

@@ -25,6 +25,8 @@ CH_E_NOT_FOUND = 10
 CH_COUNT_DOMAIN_ERROR = 0xFFFFFFFF
 CH_COUNT_INVALID = 0xFFFFFFFD
 CH_MAX_POINTS = 0x7FFFFFFF
+CH_EXTREMES_FUSED = 0
+CH_EXTREMES_TWO_KERNELS = 1
 
 STATUS_NAMES = {
     0: "CH_OK", 1: "CH_E_INVALID_ARG", 2: "CH_E_DOMAIN", 3: "CH_E_CAPACITY", 4: "CH_E_NOMEM",
@@ -73,6 +75,10 @@ SIGNATURES = {
     "ch_hull_workspace_bytes": (SZ, [U32]),
     "ch_filter": (I32, [P, P, U32, P, P, P, P, P, SZ, P]),
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
+    "ch_gpufilter_workspace_bytes": (SZ, [U32]),
+    "ch_hull_queues_workspace_bytes": (SZ, [U32]),
+    "ch_gpufilter": (I32, [P, P, U32, I32, P, P, P, P, SZ, P]),
+    "ch_hull_queues": (I32, [P, P, U32, I32, P, U32, ctypes.POINTER(U32), P, P, SZ, P]),
     "ch_diag_read_stream": (I32, [P, P, SZ, U32, P]),
     "ch_last_hull_info": (I32, [P, ctypes.POINTER(HullInfo)]),
     "ch_hull_batch_workspace_bytes": (SZ, [U32, U64]),

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libconvhull.so")
-SOURCES = ["ch_filter.hip", "ch_hull.hip", "ch_refine.hip", "ch_api.hip", "ch_serve.hip", "ch_diag.hip"]
+SOURCES = ["ch_filter.hip", "ch_hull.hip", "ch_refine.hip", "ch_queues.hip", "ch_api.hip", "ch_serve.hip",
+           "ch_diag.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -58,11 +58,28 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
-                                    uint32_t sample_grid, hipStream_t st);
+                                    uint32_t sample_grid, hipStream_t st, LaunchHook* hk);
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
-                                  hipStream_t st);
+                                  hipStream_t st, LaunchHook* hk);
+hipError_t launch_axis_extremes(const float* xy, uint32_t n, uint32_t head, double* partials,
+                                uint32_t* part_bad, uint32_t blocks, Header* hdr, hipStream_t st);
+hipError_t launch_corner_extremes(const float* xy, uint32_t n, uint32_t head, double* partials,
+                                  uint32_t blocks, const Header* hdr, hipStream_t st);
+hipError_t launch_list_chains(int NL, Rec* A, Rec* B, size_t cap, const uint32_t* begin,
+                              const uint32_t* len, uint32_t lower_mask, uint32_t* wcnt,
+                              uint32_t* pack, uint32_t* fold, hipStream_t st);
+hipError_t launch_queue_split(const uint8_t* labels, uint32_t n, const Header* hdr, uint32_t* qblk,
+                              QState* qs, uint32_t* qidx, hipStream_t st);
+hipError_t launch_queue_order(const float* xy, uint32_t n, const uint32_t* qidx, const QState* qs,
+                              const Header* hdr, uint64_t* bot, uint64_t* top, hipStream_t st);
+hipError_t launch_queue_lists(const uint64_t* bot, const uint64_t* top, uint32_t* colcnt,
+                              Rec* lists, size_t cap, const Header* hdr, QState* qs,
+                              hipStream_t st);
+hipError_t launch_queue_union(const Rec* lists, size_t cap, const QState* qs, const Header* hdr,
+                              Result* res, uint32_t* res_idx, uint32_t res_cap, Result* host,
+                              uint32_t* host_idx, uint32_t host_n, hipStream_t st);
 }  // namespace chk
 
 using namespace chk;
@@ -179,6 +196,27 @@ struct ProfScope {
   }
 };
 
+// The same events per kernel of a multi-kernel launcher.
+struct ProfHook final : LaunchHook {
+  ch_ctx* ctx;
+  hipStream_t st;
+  int stat = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfHook(ch_ctx* c, hipStream_t s) : ctx(c), st(s) {}
+  void begin(const char* name) override {
+    stat = stat_index(ctx, name);
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  void end() override {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, st);
+    ctx->pending.push_back({stat, a, b});
+    a = b = nullptr;
+  }
+};
+
 void prof_collect(ch_ctx* ctx, hipStream_t st) {
   if (!ctx->prof || ctx->pending.empty()) return;
   (void)hipStreamSynchronize(st);
@@ -251,6 +289,46 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
     else
       e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
                         at<uint32_t>(ws, L.staging), st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "filter launch");
+  return CH_OK;
+}
+
+// Alg. 2 with the chosen extreme search: the octagon in the header, the
+// ordered survivor indices, their count and (labels non-null) the label of
+// every point. CH_EXTREMES_FUSED is ch_filter's path; the two-kernel search
+// (Sec. III) replaces pass 1 by its two reductions on the same grid.
+ch_status run_gpufilter(ch_ctx* ctx, const float* d_xy, uint32_t n, int mode, uint32_t* surv,
+                        uint32_t* count_out, uint8_t* labels, void* ws, const Layout& L,
+                        hipStream_t st) {
+  if (mode == CH_EXTREMES_FUSED) return run_filter(ctx, d_xy, n, surv, count_out, labels, ws, L, st);
+  const uint32_t head = (reinterpret_cast<uintptr_t>(d_xy) & 15u) ? 1u : 0u;
+  Header* hdr = at<Header>(ws, L.hdr);
+  Result* res = at<Result>(ws, L.res);
+  const uint32_t g1 = reduce_blocks(n, ctx->reduce_max_blocks);
+  const uint32_t g2 = filter_blocks(n, ctx->filter_max_blocks);
+  double* partials = at<double>(ws, L.partials);
+  uint32_t* part_bad = at<uint32_t>(ws, L.part_bad);
+  hipError_t e;
+  {
+    ProfScope p(ctx, st, "axis_extremes");
+    e = launch_axis_extremes(d_xy, n, head, partials, part_bad, g1, hdr, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "axis extremes launch");
+  {
+    ProfScope p(ctx, st, "corner_extremes");
+    e = launch_corner_extremes(d_xy, n, head, partials, g1, hdr, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "corner extremes launch");
+  {
+    ProfScope p(ctx, st, "oct_build");
+    e = launch_oct_build(partials, part_bad, g1, hdr, res, at<uint64_t>(ws, L.tstat), g2, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "oct_build launch");
+  {
+    ProfScope p(ctx, st, "filter_compact");
+    e = launch_filter(d_xy, n, head, hdr, at<uint64_t>(ws, L.tstat), g2, surv, count_out, labels,
+                      at<uint32_t>(ws, L.staging), st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "filter launch");
   return CH_OK;
@@ -368,19 +446,15 @@ ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
   SetState* sets = at<SetState>(d_ws, L.sets);
   Rec* recA = at<Rec>(d_ws, L.recA);
   Rec* recB = at<Rec>(d_ws, L.recB);
-  hipError_t e;
-  {
-    ProfScope ps(ctx, st, "batch_filter");
-    e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
-                                 at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles), recA,
-                                 recB, p.pass_blocks, p.sample_min, (uint32_t)ctx->cu_count * 4, st);
-  }
+  ProfHook hook(ctx, st);
+  LaunchHook* hk = ctx->prof ? &hook : nullptr;
+  hipError_t e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
+                                          at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles),
+                                          recA, recB, p.pass_blocks, p.sample_min,
+                                          (uint32_t)ctx->cu_count * 4, st, hk);
   if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
-  {
-    ProfScope ps(ctx, st, "batch_hull");
-    e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
-                               d_hull_idx, d_hull_count, p.hull_blocks, st);
-  }
+  e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
+                             d_hull_idx, d_hull_count, p.hull_blocks, st, hk);
   if (e != hipSuccess) return hip_fail(ctx, e, "batch hull launch");
   return CH_OK;
 }
@@ -649,6 +723,140 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     std::memcpy(h_hull_idx, hidx, size_t(h) * 4);
   } else {
     hipError_t e = hipMemcpyAsync(h_hull_idx, res_idx, size_t(h) * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hull copy");
+  }
+  return CH_OK;
+}
+
+size_t ch_gpufilter_workspace_bytes(uint32_t n) { return qlayout(n).gpufilter_end; }
+size_t ch_hull_queues_workspace_bytes(uint32_t n) { return qlayout(n).total; }
+
+ch_status ch_gpufilter(ch_ctx* ctx, const float* d_xy, uint32_t n, int extremes_mode,
+                       uint8_t* d_label, ch_octagon* d_oct, uint32_t* d_count, void* d_ws,
+                       size_t ws_bytes, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (ch_status s = check_points(ctx, d_xy, n)) return s;
+  if (extremes_mode != CH_EXTREMES_FUSED && extremes_mode != CH_EXTREMES_TWO_KERNELS)
+    return fail(ctx, CH_E_INVALID_ARG, "unknown extremes mode %d", extremes_mode);
+  if (n && !d_label) return fail(ctx, CH_E_INVALID_ARG, "d_label is NULL");
+  const QLayout Q = qlayout(n);
+  if (!d_ws || ws_bytes < Q.gpufilter_end)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", Q.gpufilter_end, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(n);
+  uint32_t* count = d_count ? d_count : &at<Header>(d_ws, L.hdr)->count;
+  if (n == 0) {
+    if (d_count) {
+      hipError_t e = launch_set_u32(d_count, 0u, st);
+      if (e != hipSuccess) return hip_fail(ctx, e, "set count");
+    }
+    return CH_OK;
+  }
+  if (ch_status s = run_gpufilter(ctx, d_xy, n, extremes_mode, at<uint32_t>(d_ws, Q.surv), count,
+                                  d_label, d_ws, L, st))
+    return s;
+  if (d_oct) {
+    ProfScope p(ctx, st, "oct_out");
+    hipError_t e = launch_oct_out(at<Header>(d_ws, L.hdr), d_oct, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "oct_out launch");
+  }
+  prof_collect(ctx, st);
+  return CH_OK;
+}
+
+ch_status ch_hull_queues(ch_ctx* ctx, const float* d_xy, uint32_t n, int extremes_mode,
+                         uint32_t* h_hull_idx, uint32_t cap, uint32_t* h_out, uint32_t* h_qcount,
+                         void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (ch_status s = check_points(ctx, d_xy, n)) return s;
+  if (extremes_mode != CH_EXTREMES_FUSED && extremes_mode != CH_EXTREMES_TWO_KERNELS)
+    return fail(ctx, CH_E_INVALID_ARG, "unknown extremes mode %d", extremes_mode);
+  if (!h_out) return fail(ctx, CH_E_INVALID_ARG, "h_out is NULL");
+  if (cap && !h_hull_idx) return fail(ctx, CH_E_INVALID_ARG, "h_hull_idx is NULL");
+  const QLayout Q = qlayout(n);
+  if (n && (!d_ws || ws_bytes < Q.total))
+    return fail(ctx, CH_E_INVALID_ARG, "workspace needs %zu bytes, got %zu", Q.total, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
+    return fail(ctx, CH_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (n == 0) {
+    *h_out = 0;
+    if (h_qcount) std::memset(h_qcount, 0, 4 * sizeof(uint32_t));
+    return CH_OK;
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, CH_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(n);
+  Header* hdr = at<Header>(d_ws, L.hdr);
+  Result* res = at<Result>(d_ws, L.res);
+  uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
+  uint8_t* labels = at<uint8_t>(d_ws, Q.labels);
+  QState* qs = at<QState>(d_ws, Q.qstate);
+  const size_t lcap = size_t(kColumns) + 2;
+  Rec* lstA = at<Rec>(d_ws, Q.lstA);
+  const uint32_t pin_n = hull_cap(n) < kPinIdx ? hull_cap(n) : kPinIdx;
+  Result* dres_host = reinterpret_cast<Result*>(ctx->pinned_dev);
+  uint32_t* didx_host = ctx->pinned_dev ? reinterpret_cast<uint32_t*>(ctx->pinned_dev + kResBytes) : nullptr;
+  if (ch_status s = run_gpufilter(ctx, d_xy, n, extremes_mode, at<uint32_t>(d_ws, Q.surv),
+                                  &hdr->count, labels, d_ws, L, st))
+    return s;
+  hipError_t e;
+  {
+    ProfScope p(ctx, st, "queue_split");
+    e = launch_queue_split(labels, n, hdr, at<uint32_t>(d_ws, Q.qblk), qs, at<uint32_t>(d_ws, Q.qidx),
+                           st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue split launch");
+  {
+    ProfScope p(ctx, st, "queue_order");
+    e = launch_queue_order(d_xy, n, at<uint32_t>(d_ws, Q.qidx), qs, hdr, at<uint64_t>(d_ws, Q.colbot),
+                           at<uint64_t>(d_ws, Q.coltop), st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue order launch");
+  {
+    ProfScope p(ctx, st, "queue_lists");
+    e = launch_queue_lists(at<uint64_t>(d_ws, Q.colbot), at<uint64_t>(d_ws, Q.coltop),
+                           at<uint32_t>(d_ws, Q.colcnt), lstA, lcap, hdr, qs, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue lists launch");
+  {
+    // Queues 1, 2 feed the upper arcs, 3, 4 the lower ones.
+    ProfScope p(ctx, st, "queue_hulls");
+    e = launch_list_chains(4, lstA, at<Rec>(d_ws, Q.lstB), lcap, qs->begin, qs->len, 0xCu,
+                           at<uint32_t>(d_ws, Q.wcnt), qs->pack, qs->fold, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue hulls launch");
+  {
+    ProfScope p(ctx, st, "queue_union");
+    e = launch_queue_union(lstA, lcap, qs, hdr, res, res_idx, hull_cap(n), dres_host, didx_host,
+                           pin_n, st);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue union launch");
+  const Result* hres = reinterpret_cast<const Result*>(ctx->pinned);
+  const uint32_t* hidx = reinterpret_cast<const uint32_t*>(ctx->pinned + kResBytes);
+  if (!ctx->pinned_dev) e = hipMemcpyAsync(ctx->pinned, res, kResBytes + 4 * size_t(pin_n),
+                                           hipMemcpyDeviceToHost, st);
+  uint32_t qc[4] = {0, 0, 0, 0};
+  if (e == hipSuccess && h_qcount) e = hipMemcpyAsync(qc, qs->count, sizeof qc, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "queue hull");
+  prof_collect(ctx, st);
+  if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
+  if (hres->status != RES_DONE) return fail(ctx, CH_E_DEVICE, "queue hull status %u", hres->status);
+  const uint32_t h = hres->h;
+  if (h > hull_cap(n)) return fail(ctx, CH_E_DEVICE, "queue hull of %u vertices from %u points", h, n);
+  *h_out = h;
+  if (h_qcount) std::memcpy(h_qcount, qc, sizeof qc);
+  if (h > cap) return fail(ctx, CH_E_CAPACITY, "hull has %u vertices, capacity %u", h, cap);
+  if (h <= pin_n) {
+    std::memcpy(h_hull_idx, hidx, size_t(h) * 4);
+  } else {
+    e = hipMemcpyAsync(h_hull_idx, res_idx, size_t(h) * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hull copy");
   }

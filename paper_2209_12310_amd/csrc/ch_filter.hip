@@ -263,13 +263,8 @@ __device__ void build_octagon_wave(const Keys& k, Header* hdr, Result* res, uint
   reset_call_state(hdr, res, true);
 }
 
-// Pass 1: persistent grid. Each wave streams batches of kU rows of 64 pairs
-// (kU coalesced 1 KiB loads per batch) and issues the next batch's loads
-// before reducing the current one, so every wave keeps 4-8 KiB in flight.
-// Lanes past the end re-read the last pair: duplicates do not move an
-// extreme. head = 1 when xy is 8 mod 16 bytes aligned: point 0 is then read
-// on its own and the float4 stream starts at point 1. Each block writes its 8
-// keys and a domain flag; k_oct_build combines them.
+// Rows of 64 pairs per streaming batch of passes 1 and 2 (kU coalesced 1 KiB
+// loads; with the next batch in flight every wave keeps 4-8 KiB outstanding).
 constexpr int kU = 4;
 // Rows per batch of the fused hull pass, which runs with fewer workgroups
 // (it is launched with about one per CU: fewer, longer streams keep the
@@ -287,12 +282,13 @@ struct IntC {
   static constexpr int value = M;
 };
 
-__global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
-                                                    uint32_t head, double* __restrict__ partials,
-                                                    uint32_t* __restrict__ part_bad) {
-  Keys k;
-  keys_init(k);
-  bool bad = false;
+// One streaming read of all n points by a persistent grid, handing every
+// point to acc.add(x, y, bad). Each wave streams batches of kU rows of 64
+// pairs and issues the next batch's loads before reducing the current one.
+// Lanes past the end re-read the last pair (duplicates move no extreme).
+template <class Acc>
+__device__ __forceinline__ void stream_points(const float* __restrict__ xy, uint32_t n,
+                                              uint32_t head, Acc& acc, bool& bad) {
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>(xy + 2 * head);
   const uint32_t nfull = (n - head) >> 1;
   const int lane = threadIdx.x & 63;
@@ -321,8 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        keys_add(k, cur[u].x, cur[u].y, bad);
-        keys_add(k, cur[u].z, cur[u].w, bad);
+        acc.add(cur[u].x, cur[u].y, bad);
+        acc.add(cur[u].z, cur[u].w, bad);
       }
       if (!more) break;
 #pragma unroll
@@ -331,18 +327,43 @@ __global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (head) keys_add(k, xy[0], xy[1], bad);
-    if ((n - head) & 1) keys_add(k, xy[2 * (n - 1)], xy[2 * (n - 1) + 1], bad);
+    if (head) acc.add(xy[0], xy[1], bad);
+    if ((n - head) & 1) acc.add(xy[2 * (n - 1)], xy[2 * (n - 1) + 1], bad);
   }
+}
+
+// The block's domain flag (any lane saw a bad value), valid in every thread.
+__device__ __forceinline__ uint32_t block_any(bool bad) {
   const uint64_t badmask = __ballot(bad);
   __shared__ uint32_t s_bad;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  if (lane == 0 && badmask) s_bad = 1;
-  block_keys(k);
+  if ((threadIdx.x & 63) == 0 && badmask) s_bad = 1;
+  __syncthreads();
+  return s_bad;
+}
+
+// Accumulator of the one-read search: all eight slot keys.
+struct AccAll {
+  Keys k;
+  __device__ __forceinline__ void add(float x, float y, bool& bad) { keys_add(k, x, y, bad); }
+};
+
+// Pass 1: persistent grid. Each block writes its 8 keys and a domain flag;
+// k_oct_build combines them. head = 1 when xy is 8 mod 16 bytes aligned:
+// point 0 is then read on its own and the float4 stream starts at point 1.
+__global__ __launch_bounds__(kBlock) void k_reduce8(const float* __restrict__ xy, uint32_t n,
+                                                    uint32_t head, double* __restrict__ partials,
+                                                    uint32_t* __restrict__ part_bad) {
+  AccAll acc;
+  keys_init(acc.k);
+  bool bad = false;
+  stream_points(xy, n, head, acc, bad);
+  const uint32_t bflag = block_any(bad);
+  block_keys(acc.k);
   if (threadIdx.x == 0) {
-    keys_to_array(k, partials + size_t(blockIdx.x) * 8);
-    part_bad[blockIdx.x] = s_bad;
+    keys_to_array(acc.k, partials + size_t(blockIdx.x) * 8);
+    part_bad[blockIdx.x] = bflag;
   }
 }
 
@@ -411,6 +432,123 @@ __global__ __launch_bounds__(kBlock) void k_oct_build(const double* __restrict__
   const uint32_t bad = combine_partials(partials, part_bad, nparts, k);
   for (uint32_t i = threadIdx.x; i < ntstat; i += blockDim.x) tstat[i] = 0ull;
   if (threadIdx.x < 64) build_octagon_wave(k, hdr, res, bad);
+}
+
+// ------------------------------------------- the extreme search in two kernels
+//
+// Sec. III runs findExtremes on the GPU as two reductions in succession: one
+// for the four axis extremes, then one for the point of least Manhattan
+// distance to each corner of the box those four span (it needs the first
+// result). ch_gpufilter and ch_hull_queues can run it that way, beside the
+// one-read search above:
+//   k_axis4    max/min of kE = (x, y) and kN = (y, -x): E, W, N, S, and the
+//              domain check (the same keys and tie-breaks as pass 1);
+//   k_axis_box one workgroup: combine, decode the four points, keep the box;
+//   k_corner4  per corner c, the largest (-d_c, g): d_c = |c.x - x| + |c.y - y|
+//              the Manhattan distance, g the slot's counter-clockwise
+//              tie-break. On output each key is moved to pass 1's form by the
+//              corner's constant (inside the box, -d_c is +-x +-y minus a
+//              constant), so k_oct_build and every later stage see the
+//              same partials either way and the octagon is identical.
+struct AccAxis {
+  double mxE, mnE, mxN, mnN;
+  __device__ __forceinline__ void add(float x, float y, bool& bad) {
+    const float tx = x * kGridF, ty = y * kGridF;
+    bad |= (tx != __builtin_rintf(tx)) | (ty != __builtin_rintf(ty));
+    const double dx = x, dy = y;
+    const double kE = __builtin_fma(dx, kShift, dy);
+    const double kN = __builtin_fma(dy, kShift, -dx);
+    mxE = __builtin_fmax(mxE, kE); mnE = __builtin_fmin(mnE, kE);
+    mxN = __builtin_fmax(mxN, kN); mnN = __builtin_fmin(mnN, kN);
+  }
+};
+
+struct AccCorner {
+  double ex, wx, ny, sy;          // the box (E.x, W.x, N.y, S.y)
+  double kNE, kNW, kSW, kSE;      // max of -d * 2^22 + g per corner
+  __device__ __forceinline__ void add(float x, float y, bool&) {
+    const double dx = x, dy = y;
+    const double dNE = __builtin_fabs(ex - dx) + __builtin_fabs(ny - dy);
+    const double dNW = __builtin_fabs(wx - dx) + __builtin_fabs(ny - dy);
+    const double dSW = __builtin_fabs(wx - dx) + __builtin_fabs(sy - dy);
+    const double dSE = __builtin_fabs(ex - dx) + __builtin_fabs(sy - dy);
+    kNE = __builtin_fmax(kNE, __builtin_fma(-dNE, kShift, dy - dx));
+    kNW = __builtin_fmax(kNW, __builtin_fma(-dNW, kShift, -(dx + dy)));
+    kSW = __builtin_fmax(kSW, __builtin_fma(-dSW, kShift, dx - dy));
+    kSE = __builtin_fmax(kSE, __builtin_fma(-dSE, kShift, dx + dy));
+  }
+};
+
+// First reduction: the axis keys, written as 8-slot partials whose corner
+// slots hold the neutral values, and the domain flags.
+__global__ __launch_bounds__(kBlock) void k_axis4(const float* __restrict__ xy, uint32_t n,
+                                                  uint32_t head, double* __restrict__ partials,
+                                                  uint32_t* __restrict__ part_bad) {
+  const double inf = __builtin_inf();
+  AccAxis acc{-inf, inf, -inf, inf};
+  bool bad = false;
+  stream_points(xy, n, head, acc, bad);
+  const uint32_t bflag = block_any(bad);
+  Keys k;
+  keys_init(k);
+  k.mxE = acc.mxE; k.mnE = acc.mnE; k.mxN = acc.mxN; k.mnN = acc.mnN;
+  block_keys(k);
+  if (threadIdx.x == 0) {
+    keys_to_array(k, partials + size_t(blockIdx.x) * 8);
+    part_bad[blockIdx.x] = bflag;
+  }
+}
+
+// One workgroup between the two reductions: the four axis extremes and
+// their box.
+__global__ __launch_bounds__(kBlock) void k_axis_box(const double* __restrict__ partials,
+                                                     const uint32_t* __restrict__ part_bad,
+                                                     uint32_t nparts, Header* __restrict__ hdr) {
+  Keys k;
+  const uint32_t bad = combine_partials(partials, part_bad, nparts, k);
+  if (threadIdx.x != 0) return;
+  int64_t ex, ey, wx, wy, nx, ny, sx, sy;
+  const bool ok = decode_slot(k.mxE, 0, ex, ey) && decode_slot(k.mnE, 0, wx, wy) &&
+                  decode_slot(k.mxN, 1, nx, ny) && decode_slot(k.mnN, 1, sx, sy);
+  AxisBox& a = hdr->axis;
+  a.kE_max = k.mxE; a.kE_min = k.mnE; a.kN_max = k.mxN; a.kN_min = k.mnN;
+  a.bad = (ok && !bad) ? 0u : 1u;
+  const double g = 1.0 / 1048576.0;
+  a.ex = ok ? (double)ex * g : 0.0;
+  a.wx = ok ? (double)wx * g : 0.0;
+  a.ny = ok ? (double)ny * g : 0.0;
+  a.sy = ok ? (double)sy * g : 0.0;
+}
+
+// Second reduction: the corner keys, moved to pass 1's form and written with
+// the combined axis keys as full 8-slot partials (the domain flags stay
+// those of the first reduction, which ran on the same grid).
+__global__ __launch_bounds__(kBlock) void k_corner4(const float* __restrict__ xy, uint32_t n,
+                                                    uint32_t head, const Header* __restrict__ hdr,
+                                                    double* __restrict__ partials) {
+  const AxisBox& a = hdr->axis;
+  const double inf = __builtin_inf();
+  AccCorner acc{a.ex, a.wx, a.ny, a.sy, -inf, -inf, -inf, -inf};
+  bool unused = false;
+  stream_points(xy, n, head, acc, unused);
+  Keys k;
+  keys_init(k);
+  k.mxNE = acc.kNE; k.mxSE = acc.kSE;
+  k.mnNE = -acc.kSW;  // block_keys maximises mx* and minimises mn*
+  k.mnSE = -acc.kNW;
+  block_keys(k);
+  if (threadIdx.x == 0) {
+    // -d_NE = (x+y) - (E.x + N.y); -d_SW = (W.x + S.y) - (x+y);
+    // -d_SE = (x-y) - (E.x - S.y); -d_NW = (W.x - N.y) - (x-y). Every term is
+    // a multiple of 2^-20 below 2^24, so these sums are exact.
+    Keys o;
+    o.mxE = a.kE_max; o.mnE = a.kE_min; o.mxN = a.kN_max; o.mnN = a.kN_min;
+    o.mxNE = k.mxNE + (a.ex + a.ny) * kShift;
+    o.mnNE = k.mnNE + (a.wx + a.sy) * kShift;
+    o.mxSE = k.mxSE + (a.ex - a.sy) * kShift;
+    o.mnSE = k.mnSE + (a.wx - a.ny) * kShift;
+    keys_to_array(o, partials + size_t(blockIdx.x) * 8);
+  }
 }
 
 // ---------------------------------------------------------------- pass 2
@@ -1537,6 +1675,17 @@ hipError_t launch_reduce8(const float* xy, uint32_t n, uint32_t head, double* pa
   return hipGetLastError();
 }
 
+hipError_t launch_axis_extremes(const float* xy, uint32_t n, uint32_t head, double* partials,
+                                uint32_t* part_bad, uint32_t blocks, Header* hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_axis4, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, partials, part_bad);
+  hipLaunchKernelGGL(k_axis_box, dim3(1), dim3(kBlock), 0, st, partials, part_bad, blocks, hdr);
+  return hipGetLastError();
+}
+hipError_t launch_corner_extremes(const float* xy, uint32_t n, uint32_t head, double* partials,
+                                  uint32_t blocks, const Header* hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_corner4, dim3(blocks), dim3(kBlock), 0, st, xy, n, head, hdr, partials);
+  return hipGetLastError();
+}
 hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, uint32_t nparts,
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
                             hipStream_t st) {
@@ -1598,17 +1747,27 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
-                                    uint32_t sample_grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
-                     sets, tiles);
-  hipError_t e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st);
+                                    uint32_t sample_grid, hipStream_t st, LaunchHook* hk) {
+  hooked(hk, "batch_plan", [&] {
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
+                       sets, tiles);
+  });
+  hipError_t e = hipSuccess;
+  hooked(hk, "batch_sample",
+         [&] { e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st); });
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
-                     cand);
-  hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
-                     nsets, bh, sets);
-  hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets, cand,
-                     recs);
+  hooked(hk, "batch_pass", [&] {
+    hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
+                       cand);
+  });
+  hooked(hk, "batch_octagon", [&] {
+    hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
+                       nsets, bh, sets);
+  });
+  hooked(hk, "batch_cand", [&] {
+    hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets, cand,
+                       recs);
+  });
   return hipGetLastError();
 }
 

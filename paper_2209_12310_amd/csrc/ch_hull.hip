@@ -919,29 +919,29 @@ __device__ uint32_t window_chain(WinSmem<kWin>& sm, uint32_t u) {
   return par_chain<LOWER, maxc<kWin>()>(sm.px, sm.py, sm.pi, sm.px, sm.py, sm.pi, u, sm.cnt, sm.wij);
 }
 
-// Window chains of the two column lists: workgroup b < kWinPerList takes
-// window b of the lower list, the others window b - kWinPerList of the upper
-// list. The list lengths come from the column emission (res->lcount,
-// res->ucount); a workgroup past its list's end returns at once. Window k
-// covers [k*kWin, (k+1)*kWin); its chain goes to the window's start in dst,
-// its length to wcnt[b].
-__global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src_lo,
-                                                   const Rec* __restrict__ src_up,
-                                                   const Result* __restrict__ res,
-                                                   Rec* __restrict__ dst_lo,
-                                                   Rec* __restrict__ dst_up,
+// Window chains of NL x-sorted lists (list q holds len[q] records from
+// src + q * cap + begin[q]; begin may be null for 0; bit q of lower_mask
+// selects its lower chain, else the upper one). Workgroup b takes window
+// b % kWinPerList of list b / kWinPerList; past its list's end it returns at
+// once. Window k covers [k*kWin, (k+1)*kWin); its chain goes to the window's
+// start in dst + q * cap, its length to wcnt[b].
+__global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src,
+                                                   Rec* __restrict__ dst, size_t cap,
+                                                   const uint32_t* __restrict__ begin,
+                                                   const uint32_t* __restrict__ len,
+                                                   uint32_t lower_mask,
                                                    uint32_t* __restrict__ wcnt) {
   __shared__ WinSmem<kWin> sm;
-  const bool lower = blockIdx.x < kWinPerList;
-  const uint32_t k = lower ? blockIdx.x : blockIdx.x - kWinPerList;
-  const uint32_t c = lower ? res->lcount : res->ucount;
+  const uint32_t q = blockIdx.x / kWinPerList, k = blockIdx.x % kWinPerList;
+  const bool lower = (lower_mask >> q) & 1u;
+  const uint32_t c = len[q];
   const uint32_t lo = k * (uint32_t)kWin;
   if (lo >= c) return;
   const uint32_t u = c - lo < (uint32_t)kWin ? c - lo : (uint32_t)kWin;
-  const Rec* src = lower ? src_lo : src_up;
-  Rec* dst = lower ? dst_lo : dst_up;
+  const Rec* s = src + q * cap + (begin ? begin[q] : 0u) + lo;
+  Rec* d = dst + q * cap + lo;
   for (uint32_t i = threadIdx.x; i < u; i += kBlock) {
-    const Rec r = src[lo + i];
+    const Rec r = s[i];
     sm.px[i] = r.x; sm.py[i] = r.y; sm.pi[i] = r.i;
   }
   __syncthreads();
@@ -949,35 +949,33 @@ __global__ __launch_bounds__(kBlock) void k_window(const Rec* __restrict__ src_l
   for (uint32_t i = threadIdx.x; i < h; i += kBlock) {
     Rec r;
     r.x = sm.px[i]; r.y = sm.py[i]; r.i = sm.pi[i]; r.pad = 0;
-    dst[lo + i] = r;
+    d[i] = r;
   }
   if (threadIdx.x == 0) wcnt[blockIdx.x] = h;
 }
 
 // Concatenate the window chains of each list in order (same grid as
 // k_window): window k's chain moves to the sum of the chain lengths before
-// it; the last window of a list records the packed length in res->pack_cnt.
-__global__ __launch_bounds__(kBlock) void k_window_pack(const Rec* __restrict__ src_lo,
-                                                        const Rec* __restrict__ src_up,
+// it; the last window of list q records the packed length in pack[q].
+__global__ __launch_bounds__(kBlock) void k_window_pack(const Rec* __restrict__ src,
+                                                        Rec* __restrict__ dst, size_t cap,
+                                                        const uint32_t* __restrict__ len,
                                                         const uint32_t* __restrict__ wcnt,
-                                                        Result* __restrict__ res,
-                                                        Rec* __restrict__ dst_lo,
-                                                        Rec* __restrict__ dst_up) {
-  const bool lower = blockIdx.x < kWinPerList;
-  const uint32_t k = lower ? blockIdx.x : blockIdx.x - kWinPerList;
-  const uint32_t c = lower ? res->lcount : res->ucount;
+                                                        uint32_t* __restrict__ pack) {
+  const uint32_t q = blockIdx.x / kWinPerList, k = blockIdx.x % kWinPerList;
+  const uint32_t c = len[q];
   const uint32_t lo = k * (uint32_t)kWin;
   if (lo >= c) return;
-  const uint32_t* wc = wcnt + (lower ? 0u : kWinPerList);
+  const uint32_t* wc = wcnt + q * kWinPerList;
   uint32_t part = 0;
   for (uint32_t i = threadIdx.x; i < k; i += kBlock) part += wc[i];
   uint32_t off;
   block_excl_scan(part, off);
   const uint32_t h = wc[k];
-  if (threadIdx.x == 0 && c - lo <= (uint32_t)kWin) res->pack_cnt[lower ? 0 : 1] = off + h;
-  const Rec* src = lower ? src_lo : src_up;
-  Rec* dst = lower ? dst_lo : dst_up;
-  for (uint32_t i = threadIdx.x; i < h; i += kBlock) dst[off + i] = src[lo + i];
+  if (threadIdx.x == 0 && c - lo <= (uint32_t)kWin) pack[q] = off + h;
+  const Rec* s = src + q * cap + lo;
+  Rec* d = dst + q * cap;
+  for (uint32_t i = threadIdx.x; i < h; i += kBlock) d[off + i] = s[i];
 }
 
 // ------------------------------------------------ the chain of a long list
@@ -1065,16 +1063,32 @@ __device__ uint32_t fold_chain(WinSmem<kWin>& sm, const Rec* in, uint32_t m, Rec
   return r;
 }
 
-// Two workgroups: the lower chain of the packed lower list (workgroup 0) and
-// the upper chain of the packed upper list (workgroup 1), each in place.
-__global__ __launch_bounds__(kBlock) void k_fold(Rec* __restrict__ lst_lo, Rec* __restrict__ lst_up,
-                                                 Result* __restrict__ res) {
+// One workgroup per list: the chain of packed list q (pack[q] records at
+// lists + q * cap; lower when bit q of lower_mask is set), in place; its
+// length to fold[q].
+__global__ __launch_bounds__(kBlock) void k_fold(Rec* __restrict__ lists, size_t cap,
+                                                 const uint32_t* __restrict__ pack,
+                                                 uint32_t lower_mask, uint32_t* __restrict__ fold) {
   __shared__ WinSmem<kWin> sm;
-  const bool lower = blockIdx.x == 0;
-  const uint32_t m = res->pack_cnt[lower ? 0 : 1];
-  const uint32_t r = lower ? fold_chain<true>(sm, lst_lo, m, lst_lo)
-                           : fold_chain<false>(sm, lst_up, m, lst_up);
-  if (threadIdx.x == 0) res->fold_cnt[lower ? 0 : 1] = r;
+  const uint32_t q = blockIdx.x;
+  Rec* l = lists + q * cap;
+  const uint32_t m = pack[q];
+  const uint32_t r = ((lower_mask >> q) & 1u) ? fold_chain<true>(sm, l, m, l)
+                                               : fold_chain<false>(sm, l, m, l);
+  if (threadIdx.x == 0) fold[q] = r;
+}
+
+// Window chains, packing and one fold per list, for NL lists as k_window
+// describes them: the chains end up packed at the start of each list of A.
+hipError_t launch_list_chains(int NL, Rec* A, Rec* B, size_t cap, const uint32_t* begin,
+                              const uint32_t* len, uint32_t lower_mask, uint32_t* wcnt,
+                              uint32_t* pack, uint32_t* fold, hipStream_t st) {
+  hipLaunchKernelGGL(k_window, dim3(NL * kWinPerList), dim3(kBlock), 0, st, A, B, cap, begin, len,
+                     lower_mask, wcnt);
+  hipLaunchKernelGGL(k_window_pack, dim3(NL * kWinPerList), dim3(kBlock), 0, st, B, A, cap, len,
+                     wcnt, pack);
+  hipLaunchKernelGGL(k_fold, dim3(NL), dim3(kBlock), 0, st, A, cap, pack, lower_mask, fold);
+  return hipGetLastError();
 }
 
 // Final output of the large-hull path: the counter-clockwise hull (the lower
@@ -1369,15 +1383,13 @@ hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t m
   const size_t cap = size_t(kColumns) + 2;
   Rec* Alo = lstA;
   Rec* Aup = lstA + cap;
-  Rec* Blo = lstB;
-  Rec* Bup = lstB + cap;
   hipError_t e = launch_col_build(in, in_count, max_in, bot, top, colcnt, Alo, Aup, oct, res, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_window, dim3(2 * kWinPerList), dim3(kBlock), 0, st, Alo, Aup, res, Blo, Bup,
-                     wcnt);
-  hipLaunchKernelGGL(k_window_pack, dim3(2 * kWinPerList), dim3(kBlock), 0, st, Blo, Bup, wcnt, res,
-                     Alo, Aup);
-  hipLaunchKernelGGL(k_fold, dim3(2), dim3(kBlock), 0, st, Alo, Aup, res);
+  // lcount and ucount are adjacent: the two list lengths.
+  static_assert(offsetof(Result, ucount) == offsetof(Result, lcount) + 4, "list lengths");
+  e = launch_list_chains(2, lstA, lstB, cap, nullptr, &res->lcount, 1u, wcnt, res->pack_cnt,
+                         res->fold_cnt, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_large_out, dim3(1), dim3(kBlock), 0, st, Alo, Aup, res, res_idx, host,
                      host_idx, host_n);
   return hipGetLastError();
@@ -1390,26 +1402,36 @@ namespace chk {
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
-                                  hipStream_t st) {
+                                  hipStream_t st, LaunchHook* hk) {
   Rec* buf[2] = {recA, recB};
-  hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                     sets, 0, recA, hull_idx, hull_count);
+  hooked(hk, "batch_final", [&] {
+    hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                       sets, 0, recA, hull_idx, hull_count);
+  });
   for (int r = 0; r < kBatchRounds; ++r) {
-    hipLaunchKernelGGL(k_batch_round_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, bh, sets, r,
-                       rtiles);
-    hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,
-                       buf[r & 1], buf[(r + 1) & 1]);
-    if (r + 1 < kBatchRounds)
-      hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
-    else
-      hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                         sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
+    hooked(hk, "batch_round_plan", [&] {
+      hipLaunchKernelGGL(k_batch_round_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, bh, sets, r,
+                         rtiles);
+    });
+    hooked(hk, "batch_round", [&] {
+      hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,
+                         buf[r & 1], buf[(r + 1) & 1]);
+    });
+    hooked(hk, "batch_final", [&] {
+      if (r + 1 < kBatchRounds)
+        hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
+      else
+        hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
+    });
   }
   // Sets whose candidates did not shrink to one workgroup: the last round
   // wrote them to buf[kBatchRounds & 1].
-  hipLaunchKernelGGL(k_batch_large, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
-                     buf[kBatchRounds & 1], buf[(kBatchRounds + 1) & 1], hull_idx, hull_count);
+  hooked(hk, "batch_large", [&] {
+    hipLaunchKernelGGL(k_batch_large, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
+                       buf[kBatchRounds & 1], buf[(kBatchRounds + 1) & 1], hull_idx, hull_count);
+  });
   return hipGetLastError();
 }
 

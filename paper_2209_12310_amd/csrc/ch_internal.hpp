@@ -30,6 +30,22 @@ constexpr uint32_t kColBlocks = kColumns / kColChunk;
 
 constexpr uint32_t kCountDomain = 0xFFFFFFFFu;
 
+// Host-side bracket around the kernel launches of a multi-kernel launcher
+// (per-kernel timing on the launch stream); launchers take it as null when
+// timing is off.
+struct LaunchHook {
+  virtual void begin(const char* name) = 0;
+  virtual void end() = 0;
+  virtual ~LaunchHook() = default;
+};
+
+template <class F>
+inline void hooked(LaunchHook* hk, const char* name, F&& launch) {
+  if (hk) hk->begin(name);
+  launch();
+  if (hk) hk->end();
+}
+
 enum : uint32_t { RES_PENDING = 0, RES_DONE = 1, RES_MORE = 2, RES_DOMAIN = 3 };
 
 // The octagon and its edge forms, written once per call by the last block of
@@ -45,6 +61,16 @@ struct Octagon {
   uint32_t pad[2];
 };
 
+// The axis extremes of the two-kernel extreme search (the first of its two
+// reductions), read by every workgroup of the second: the combined keys and
+// the box the four points span (float units).
+struct AxisBox {
+  double kE_max, kE_min, kN_max, kN_min;
+  double ex, wx, ny, sy;  // E.x, W.x, N.y, S.y
+  uint32_t bad;           // the keys did not decode (domain error)
+  uint32_t pad[7];
+};
+
 struct Header {
   uint32_t arrive;     // pass-1 blocks finished (reset by the last one)
   uint32_t tile_ctr;   // pass-2 dynamic tile ids (reset by pass 1)
@@ -54,6 +80,7 @@ struct Header {
   uint32_t col_arrive; // column-table bookkeeping
   uint32_t pad[7];
   Octagon oct;
+  AxisBox axis;
 };
 
 // Followed directly in memory by the hull index array, so that one small
@@ -110,9 +137,9 @@ constexpr size_t kResBytes = 1024;
 static_assert(sizeof(Header) <= kHdrBytes, "header too large");
 static_assert(sizeof(Result) <= kResBytes, "result too large");
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) : kHullCapMax; }
+constexpr uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) : kHullCapMax; }
 
 // Workspace layout. ch_filter uses the prefix up to `filter_end`.
 struct Layout {
@@ -120,7 +147,7 @@ struct Layout {
   size_t surv, recA, recB, colbot, coltop, colcnt, lstA, lstB, wcnt, poly, samp, total;
 };
 
-inline Layout layout(uint32_t n) {
+constexpr Layout layout(uint32_t n) {
   Layout L{};
   size_t o = 0;
   L.hdr = o;       o += kHdrBytes;
@@ -156,6 +183,54 @@ inline Layout layout(uint32_t n) {
                                        size_t(kSampleBlocks) * kPolyMax * 16, 256);
   L.total = o;
   return L;
+}
+
+// ------------------------------------------------- Alg. 1 with its four queues
+// (ch_gpufilter, ch_hull_queues). Queue q (0..3 here, the paper's 1..4)
+// holds the points labelled q + 1 by Alg. 2's array.
+constexpr uint32_t kQBlocksMax = 1024;   // label-split workgroups
+constexpr uint32_t kQChunkMin = 4096;    // labels per split workgroup at least
+
+struct QState {
+  uint32_t count[4];   // queue sizes
+  uint32_t base[4];    // start of queue q in the queue array
+  uint32_t emit[4];    // column entries emitted into list q
+  uint32_t begin[4];   // first record of list q (1 when its start end was already there)
+  uint32_t len[4];     // records of list q, both arc ends included
+  uint32_t pack[4];    // packed window chains of list q
+  uint32_t fold[4];    // chain length of list q
+  uint32_t pad[4];
+};
+
+// Workspace of ch_gpufilter (prefix) and ch_hull_queues: the filter's layout
+// up to filter_end, the ordered survivor indices, then (queues) the label
+// array, the split counts, the queue array, the column tables and four
+// record lists in each of two buffers.
+struct QLayout {
+  size_t surv, gpufilter_end, labels, qblk, qstate, qidx, colbot, coltop, colcnt, lstA, lstB, wcnt,
+      total;
+};
+
+inline QLayout qlayout(uint32_t n) {
+  QLayout Q{};
+  const Layout L = layout(n);
+  const size_t m = n ? n : 1;
+  size_t o = L.filter_end;
+  Q.surv = o;      o = align_up(o + m * 4, 256);
+  Q.gpufilter_end = o;
+  Q.labels = o;    o = align_up(o + m + 16, 256);
+  Q.qblk = o;      o = align_up(o + size_t(kQBlocksMax) * 4 * 4, 256);
+  Q.qstate = o;    o = align_up(o + sizeof(QState), 256);
+  Q.qidx = o;      o = align_up(o + m * 4, 256);
+  Q.colbot = o;    o = align_up(o + size_t(kColumns) * 8, 256);
+  Q.coltop = o;    o = align_up(o + size_t(kColumns) * 8, 256);
+  Q.colcnt = o;    o = align_up(o + size_t(kColBlocks) * 4 * 4, 256);
+  const size_t cap = size_t(kColumns) + 2;
+  Q.lstA = o;      o = align_up(o + 4 * cap * sizeof(Rec), 256);
+  Q.lstB = o;      o = align_up(o + 4 * cap * sizeof(Rec), 256);
+  Q.wcnt = o;      o = align_up(o + 4 * (cap / 4096 + 2) * 4, 256);
+  Q.total = o;
+  return Q;
 }
 
 // ---------------------------------------------------------------- batch mode

@@ -213,3 +213,39 @@ def test_tuner_and_cache(tmp_path):
             assert np.array_equal(got_idx[off[s]: off[s] + got_cnt[s]], oracle.hull(pts)), s
     finally:
         c2.close()
+
+
+def test_batch_4096_full(ctx):
+    """The full batch workload (4096 sets, 5.84e8 points): every set's hull
+    from one ch_hull_batch call, in the launch configuration the benchmark
+    times (tuned parameters), against the oracle set by set."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    _say("batch_4096 full: generating")
+    xy, off, _ = workloads.batch_sets(4096, 3)
+    n, nsets = xy.shape[0], off.size - 1
+    t = torch.from_numpy(xy).to("cuda:0")
+    o = torch.from_numpy(off.astype(np.int64)).to("cuda:0")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    cnt = torch.empty(nsets, dtype=torch.int32, device="cuda:0")
+    ws = ctx.workspace(ctx._lib.ch_hull_batch_workspace_bytes(nsets, n))
+    _say("batch_4096 full: tuned call")
+    ctx.tune_batch(t, o, idx, cnt, ws)
+    idx.fill_(-1)
+    ctx.hull_batch_async(t, o, idx, cnt, ws)
+    got_c = cnt.cpu().numpy().view(np.uint32)
+    got_i = idx.cpu().numpy().view(np.uint32)
+    del t, idx
+    ctx._ws = None
+    torch.cuda.empty_cache()
+    _say("batch_4096 full: oracle")
+
+    def one(s):
+        a, b = int(off[s]), int(off[s + 1])
+        want = oracle.hull(xy[a:b])
+        return s, got_c[s] == want.size and np.array_equal(got_i[a: a + want.size], want)
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        bad = [s for s, ok in ex.map(one, range(nsets)) if not ok]
+    assert not bad, bad[:10]

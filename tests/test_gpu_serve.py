@@ -210,3 +210,25 @@ def test_stop_wakes_waiters(ctx, arena):
         assert np.array_equal(val, want)
     else:
         assert val == ch._capi.CH_E_SHUTDOWN
+
+
+def test_request_at_the_top_of_the_size_range(ctx):
+    """One request of 10^7 points (the largest request size of the serving
+    workload), next to small ones, in an arena sized for it."""
+    import torch
+    _say("serve 1e7-point request")
+    big = workloads.by_kind("annulus_wide", 10_000_000, 77)
+    small = [workloads.by_kind("normal", 5000, 78 + i) for i in range(3)]
+    arena = torch.empty(6 << 30, dtype=torch.uint8, device="cuda:0")
+    srv = ctx.serve(arena, n_streams=2)
+    try:
+        assert srv.max_request_points >= big.shape[0]
+        tickets = [srv.submit(s) for s in [small[0], big] + small[1:]]
+        for s, tk in zip([small[0], big] + small[1:], tickets):
+            got, _ = srv.wait(tk)
+            assert np.array_equal(got, oracle.hull(s)), s.shape
+    finally:
+        srv.stop()
+    del arena
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
