@@ -49,6 +49,45 @@ def stage_bytes(n: int, info: dict) -> dict:
     b["total"] = sum(b.values())
     b["per_point"] = round(b["total"] / n, 3)
     return b
+
+
+def kernel_alg_bytes(name: str, n: int, info: dict):
+    """Algorithmic HBM bytes of one launch of a ch_hull kernel (None where no
+    byte model applies: one-workgroup stages bound by latency)."""
+    cand, surv = info.get("candidates", 0), info.get("survivors", 0)
+    model = {
+        "pass_fused": 8 * n + 16 * cand,          # every point once + candidate records
+        "reduce8": 8 * n,                         # pass 1
+        "filter_compact": 8 * n + 16 * surv,      # pass 2 + survivor records
+        "cand_filter": 16 * cand + 16 * surv,     # candidate records in, survivors out
+        "lg_col_init": 2 * 8 * (1 << 20),         # two 2^20-entry column tables cleared
+        "lg_col_scatter": 16 * surv,              # survivor records read (atomics into the tables)
+    }
+    return model.get(name)
+
+
+def kernel_roofline(stats: dict, n: int, info: dict, read_gbs=None) -> dict:
+    """Roofline of the dominant kernel among those with a byte model, from
+    the library's per-kernel HIP events; also names the kernel that takes the
+    most time overall."""
+    means = {k: v[1] / v[0] for k, v in stats.items() if v[0]}
+    if not means:
+        return {}
+    overall = max(means, key=lambda k: means[k] * stats[k][0])
+    modelled = [k for k in means if kernel_alg_bytes(k, n, info) is not None]
+    if not modelled:
+        return {"dominant_overall": overall}
+    dom = max(modelled, key=lambda k: means[k])
+    alg = kernel_alg_bytes(dom, n, info)
+    achieved = alg / (means[dom] * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg,
+         "mean_us": round(means[dom] * 1e3, 2), "dominant_overall": overall}
+    if read_gbs:
+        r["frac_of_read_stream"] = round(achieved / read_gbs, 4)
+    return r
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_normal_1e8.json")
 KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp",
                   "paper_2209_12310_amd/csrc/ch_device.hpp", "paper_2209_12310_amd/csrc/ch_refine.hpp",
@@ -241,7 +280,7 @@ def measure_read_stream(ctx, buf, reps: int = 10) -> dict:
             "kernel": "ch_diag_read_stream: 16-byte non-temporal loads, 4 per thread per step"}
 
 
-def bench_single(ctx, name: str, steps: int, warmup: int) -> dict:
+def bench_single(ctx, name: str, steps: int, warmup: int, read_gbs=None) -> dict:
     """ch_hull end to end on one more single-set configuration."""
     import torch
 
@@ -263,11 +302,22 @@ def bench_single(ctx, name: str, steps: int, warmup: int) -> dict:
     ms = (time.perf_counter() - t0) / steps * 1e3
     info = ctx.last_hull_info()
     moved = stage_bytes(n, info)["total"] + 16 * info["survivors"]
+    # Kernel durations in a second region (library events on the launch stream).
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    for _ in range(steps):
+        ctx.hull(t)
+    torch.cuda.synchronize()
+    ctx.profile_enable(False)
+    stats = ctx.profile_read()
     del t
     return {"workload": name, "n": n, "ms_per_step": round(ms, 4), "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
             "bytes_per_point": round(moved / n, 3),
             "hbm_frac": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "octagon_survivors": survivors, "hull_info": info, "h": int(hull.size)}
+            "octagon_survivors": survivors, "hull_info": info, "h": int(hull.size),
+            "kernels_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in stats.items() if v[0]},
+            "kernel_launches_per_step": {k: round(v[0] / steps, 2) for k, v in stats.items() if v[0]},
+            "roofline": kernel_roofline(stats, n, info, read_gbs)}
 
 
 def pct(vals, q):
@@ -278,9 +328,12 @@ def pct(vals, q):
 def bench_batch(ctx, steps: int, warmup: int) -> dict:
     """Batched mode on 4096 sets (log-uniform sizes in [1e3, 1e6], kinds
     uniform / normal / annulus 0.49-0.5, seed 3): parameters from the
-    autotuner, then one ch_hull_batch call per step, timed with events on the
-    launch stream; compared with one ch_hull call per set on the same
-    device-resident points."""
+    autotuner, then the ch_hull_batch call captured once in a HIP graph and
+    the graph replayed once per step, timed with events on the replay
+    stream (the headline batch figure); eager calls are timed beside it.
+    Every set of a batch completes when the launch sequence does, so the
+    per-set latency is the batch latency. Compared with one ch_hull call per
+    set on the same device-resident points."""
     import numpy as np
     import torch
 
@@ -301,19 +354,61 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
     for _ in range(warmup):
         ctx.hull_batch_async(t, o, idx, cnt, ws)
     torch.cuda.synchronize()
-    counts = cnt.cpu().numpy().view(np.uint32)
+    counts = cnt.cpu().numpy().view(np.uint32).copy()
     assert (counts < 0xFFFFFFF0).all(), "batch returned an error code"
-    lat = []
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    hull_idx_eager = idx.cpu().numpy().view(np.uint32).copy()
+
+    def timed(launch):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            launch()
+            b.record()
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in ev], (time.perf_counter() - w0) / steps
+
+    lat_eager, wall_eager = timed(lambda: ctx.hull_batch_async(t, o, idx, cnt, ws))
+    # One capture, replayed per step (the launch sequence holds no host
+    # synchronisation and no memset node).
+    log("batch: graph capture and replays")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            ctx.hull_batch_async(t, o, idx, cnt, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(2):
+        g.replay()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record()
+    lat, wall = timed(g.replay)
+    same = (np.array_equal(cnt.cpu().numpy().view(np.uint32), counts) and
+            np.array_equal(idx.cpu().numpy().view(np.uint32), hull_idx_eager))
+    assert same, "graph replay differs from the eager call"
+    del g
+    # Per-kernel durations (library events around each launch, eager calls).
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    for _ in range(steps):
         ctx.hull_batch_async(t, o, idx, cnt, ws)
-        b.record()
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    lat = [a.elapsed_time(b) for a, b in ev]
+    ctx.profile_enable(False)
+    stats = ctx.profile_read()
+    kernels = {k: {"launches_per_batch": round(v[0] / steps, 2), "ms_per_batch": round(v[1] / steps, 4)}
+               for k, v in stats.items() if v[0]}
+    # Roofline of the single read over all sets (k_batch_pass): 8 B per point
+    # (candidate records written are not counted: a lower bound).
+    pass_ms = stats.get("batch_pass", (0, 0.0))[1] / max(stats.get("batch_pass", (1, 0))[0], 1)
+    roof = None
+    if pass_ms > 0:
+        ach = 8 * n / (pass_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "batch_pass", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": 8 * n,
+                "mean_us": round(pass_ms * 1e3, 2),
+                "note": "8 B per point read; candidate records written are left out (lower bound)"}
     # Plain mode: one synchronous ch_hull per set.
     log("plain mode: one ch_hull per set")
     for s in range(min(64, nsets)):
@@ -326,13 +421,17 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
     plain = time.perf_counter() - tp
     ms = float(np.mean(lat))
     return {"workload": "batch_4096", "sets": nsets, "points": n, "steps": steps,
+            "timing": "one HIP graph replay of the captured ch_hull_batch call per step",
             "ms_per_batch": round(ms, 3), "wall_ms_per_batch": round(wall * 1e3, 3),
             "hulls_per_s": round(nsets / (ms * 1e-3), 1),
             "mpts_per_s": round(n / (ms * 1e-3) / 1e6, 1),
-            "batch_p50_ms": round(pct(lat, 50), 3), "batch_p99_ms": round(pct(lat, 99), 3),
+            "hbm_frac_8B_per_point": round(8 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "batch_latency_p50_ms": round(pct(lat, 50), 3), "batch_latency_p99_ms": round(pct(lat, 99), 3),
+            "eager_ms_per_batch": round(float(np.mean(lat_eager)), 3),
+            "eager_wall_ms_per_batch": round(wall_eager * 1e3, 3),
             "plain_ms": round(plain * 1e3, 1), "plain_hulls_per_s": round(nsets / plain, 1),
             "speedup_vs_plain": round(plain / (ms * 1e-3), 2),
-            "params": params, "tune_s": round(tune_s, 2),
+            "params": params, "tune_s": round(tune_s, 2), "kernels": kernels, "roofline": roof,
             "kinds": {k: kinds.count(k) for k in sorted(set(kinds))}}
 
 
@@ -347,13 +446,16 @@ def _serve_views(pools, sizes, kinds, seeds):
     return views
 
 
-def bench_serve(ctx, duration_s: float = 8.0, arena_gb: int = 64, streams: int = 4) -> dict:
+def bench_serve(ctx, duration_s: float = 60.0, arena_gb: int = 64, streams: int = 4,
+                plain_s: float = 15.0) -> dict:
     """Serving: Poisson arrivals of host-resident requests (sizes log-uniform
     in [1e2, 1e7], kinds uniform / normal / wide annulus, seed 4) through the
     ch_serve server; latency = completion - scheduled arrival, including
     queueing and the host-to-device copy. The rate is 0.7 x the capacity
-    measured on a saturated burst. Compared with plain mode: the same trace
-    solved one request at a time (copy, then ch_hull) on one stream."""
+    measured on a saturated burst. Compared with plain mode: the first
+    plain_s seconds of the same trace solved one request at a time (copy,
+    then ch_hull) on one stream; plain mode's capacity is below the arrival
+    rate, so its queue only grows after that."""
     import queue
     import threading
 
@@ -394,15 +496,35 @@ def bench_serve(ctx, duration_s: float = 8.0, arena_gb: int = 64, streams: int =
         th = threading.Thread(target=submitter)
         th.start()
         lat, done_max = [], 0
+        parts = np.zeros((len(views), 3))  # submit lag, queueing, service (us)
         for i in range(len(views)):
             _, tns = srv.wait(q.get())
-            lat.append((int(tns[2]) - int(sched[i])) * 1e-3)
-            done_max = max(done_max, int(tns[2]))
+            a, m, d = (int(v) for v in tns)
+            lat.append((d - int(sched[i])) * 1e-3)
+            parts[i] = ((a - int(sched[i])) * 1e-3, (m - a) * 1e-3, (d - m) * 1e-3)
+            done_max = max(done_max, d)
         th.join()
         st = srv.stats()
     finally:
         srv.stop()
     del arena
+    # Where the latency goes: per component, and the tail by request size.
+    lat_a = np.asarray(lat)
+    sz = np.asarray(sizes, dtype=np.float64)
+    tail = lat_a >= np.percentile(lat_a, 99)
+    breakdown = {
+        "submit_lag_us": {"p50": round(pct(parts[:, 0], 50), 1), "p99": round(pct(parts[:, 0], 99), 1)},
+        "queue_us": {"p50": round(pct(parts[:, 1], 50), 1), "p99": round(pct(parts[:, 1], 99), 1)},
+        "service_us": {"p50": round(pct(parts[:, 2], 50), 1), "p99": round(pct(parts[:, 2], 99), 1),
+                       "what": "admission to completion: host-to-device copy, batch kernels, hull copy back"},
+        "p99_tail": {"requests": int(tail.sum()),
+                     "median_points": int(np.median(sz[tail])),
+                     "mean_queue_us": round(float(parts[tail, 1].mean()), 1),
+                     "mean_service_us": round(float(parts[tail, 2].mean()), 1)},
+        "by_size_p99_us": {label: round(pct(lat_a[m], 99), 1) for label, m in
+                           (("lt_1e5", sz < 1e5), ("1e5_1e6", (sz >= 1e5) & (sz < 1e6)),
+                            ("ge_1e6", sz >= 1e6)) if m.any()},
+    }
     # Plain mode on the same trace: one request at a time.
     log("serve: plain mode")
     dev = torch.empty((int(max(sizes)), 2), dtype=torch.float32, device="cuda:0")
@@ -410,6 +532,8 @@ def bench_serve(ctx, duration_s: float = 8.0, arena_gb: int = 64, streams: int =
     pstart = time.monotonic_ns() + 50_000_000
     psched = pstart + (np.asarray(times) * 1e9).astype(np.int64)
     for i, v in enumerate(views):
+        if times[i] > plain_s:
+            break
         d = (int(psched[i]) - time.monotonic_ns()) * 1e-9
         if d > 0:
             time.sleep(d)
@@ -425,8 +549,11 @@ def bench_serve(ctx, duration_s: float = 8.0, arena_gb: int = 64, streams: int =
             "hulls_per_s": round(len(views) / ((done_max - start) * 1e-9), 1),
             "p50_us": round(pct(lat, 50), 1), "p99_us": round(pct(lat, 99), 1),
             "batches": st["batches"],
-            "plain_hulls_per_s": round(len(views) / ((pend - pstart) * 1e-9), 1),
+            "latency_breakdown": breakdown,
+            "plain_requests": len(plat),
+            "plain_hulls_per_s": round(len(plat) / ((pend - pstart) * 1e-9), 1),
             "plain_p50_us": round(pct(plat, 50), 1), "plain_p99_us": round(pct(plat, 99), 1),
+            "plain_trace_s": plain_s,
             "input": "pinned host memory, copied to the device inside the measured latency"}
 
 
@@ -452,6 +579,10 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true", help="skip the other single-set configurations")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-pipeline measurements")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="single-set workload of the headline line (profiling runs of other configs)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="measure batch mode alone (profiling runs of batch_4096)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -460,6 +591,15 @@ def main() -> int:
     if args.copy_calibration:
         copy_calibration()
         return 0
+    if args.only_batch:
+        import torch
+
+        import paper_2209_12310_amd as ch
+        ctx = ch.Context(0)
+        print(json.dumps({"batch": bench_batch(ctx, max(5, min(args.steps, 20)), args.warmup)}), flush=True)
+        ctx.close()
+        return 0
+    workload = args.workload
 
     import numpy as np
     import torch
@@ -467,8 +607,8 @@ def main() -> int:
     import paper_2209_12310_amd as ch
     from paper_2209_12310_amd import workloads
 
-    log(f"generating {WORKLOAD}")
-    xy = workloads.single(WORKLOAD)
+    log(f"generating {workload}")
+    xy = workloads.single(workload)
     n = xy.shape[0]
     dev = torch.device("cuda:0")
     t = torch.from_numpy(xy).to(dev)
@@ -551,9 +691,11 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "input_dtype": "f32",
+        "arithmetic": "float32 (x, y) on the 2^-20 grid in; every predicate exact in fp64 / int64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": n, "distribution": "normal mean 0.5 sigma 0.1, "
-                   "float32 on the 2^-20 grid in [0,1)", "seed": 1, "survivors": survivors,
+        "config": {"workload": workload, "n": n, "distribution": workloads.describe(workload),
+                   "seed": workloads.seed_of(workload), "survivors": survivors,
                    "h": int(hull.size)},
         "bytes_per_point_end_to_end": round(moved / n, 3),
         "hbm_frac_end_to_end": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -568,15 +710,19 @@ def main() -> int:
         out["paper_pipeline"] = bench_paper_pipeline(ctx, t, max(3, min(args.steps, 10)))
     del t
     torch.cuda.synchronize()
-    out["single_sets"] = {WORKLOAD: {"workload": WORKLOAD, "n": n, "ms_per_step": round(ms, 4),
+    out["single_sets"] = {workload: {"workload": workload, "n": n, "ms_per_step": round(ms, 4),
                                      "mpts_per_s": round(value, 1),
                                      "bytes_per_point": out["bytes_per_point_end_to_end"],
                                      "hbm_frac": out["hbm_frac_end_to_end"],
                                      "octagon_survivors": survivors, "hull_info": info,
-                                     "h": int(hull.size)}}
+                                     "h": int(hull.size), "kernels_us": {k: v["mean_us"] for k, v in kernels.items()},
+                                     "roofline": kernel_roofline(stats, n, info, read_stream["gbs"])}}
     if not args.no_extra:
         for name in ("uniform_1e8", "annulus_1e8", "uniform_1e6"):
-            out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 5)
+            if name == workload:
+                continue
+            out["single_sets"][name] = bench_single(ctx, name, max(3, min(args.steps, 20)), 5,
+                                                    read_stream["gbs"])
             torch.cuda.synchronize()
     if not args.no_batch:
         out["batch"] = bench_batch(ctx, max(5, min(args.steps, 20)), 1)

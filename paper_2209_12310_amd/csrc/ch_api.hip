@@ -51,7 +51,8 @@ hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* i
 hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
                              uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
                              uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
-                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st);
+                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st,
+                             LaunchHook* hk);
 hipError_t launch_read_stream(const void* d_buf, size_t bytes, uint32_t blocks, float* sink,
                               hipStream_t st);
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
@@ -69,7 +70,7 @@ hipError_t launch_corner_extremes(const float* xy, uint32_t n, uint32_t head, do
                                   uint32_t blocks, const Header* hdr, hipStream_t st);
 hipError_t launch_list_chains(int NL, Rec* A, Rec* B, size_t cap, const uint32_t* begin,
                               const uint32_t* len, uint32_t lower_mask, uint32_t* wcnt,
-                              uint32_t* pack, uint32_t* fold, hipStream_t st);
+                              uint32_t* pack, uint32_t* fold, hipStream_t st, LaunchHook* hk);
 hipError_t launch_queue_split(const uint8_t* labels, uint32_t n, const Header* hdr, uint32_t* qblk,
                               QState* qs, uint32_t* qidx, hipStream_t st);
 hipError_t launch_queue_order(const float* xy, uint32_t n, const uint32_t* qidx, const QState* qs,
@@ -700,11 +701,12 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     const Rec* lin = round ? rec[last_list] : srec;
     const uint32_t* lcnt = round ? &res->round_cnt[round] : &hdr->count;
     {
-      ProfScope p(ctx, st, "large_path");
+      // Per-kernel events of the large-hull path when profiling is on.
+      ProfHook hook(ctx, st);
       e = launch_large_path(lin, lcnt, cin, at<uint64_t>(d_ws, L.colbot), at<uint64_t>(d_ws, L.coltop),
                             at<uint32_t>(d_ws, L.colcnt), at<Rec>(d_ws, L.lstA),
                             at<Rec>(d_ws, L.lstB), at<uint32_t>(d_ws, L.wcnt), &hdr->oct, res,
-                            res_idx, dres_host, didx_host, pin_n, st);
+                            res_idx, dres_host, didx_host, pin_n, st, ctx->prof ? &hook : nullptr);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "large path launch");
     if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "large path");
@@ -828,7 +830,7 @@ ch_status ch_hull_queues(ch_ctx* ctx, const float* d_xy, uint32_t n, int extreme
     // Queues 1, 2 feed the upper arcs, 3, 4 the lower ones.
     ProfScope p(ctx, st, "queue_hulls");
     e = launch_list_chains(4, lstA, at<Rec>(d_ws, Q.lstB), lcap, qs->begin, qs->len, 0xCu,
-                           at<uint32_t>(d_ws, Q.wcnt), qs->pack, qs->fold, st);
+                           at<uint32_t>(d_ws, Q.wcnt), qs->pack, qs->fold, st, nullptr);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "queue hulls launch");
   {

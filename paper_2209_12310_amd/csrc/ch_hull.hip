@@ -1082,12 +1082,18 @@ __global__ __launch_bounds__(kBlock) void k_fold(Rec* __restrict__ lists, size_t
 // describes them: the chains end up packed at the start of each list of A.
 hipError_t launch_list_chains(int NL, Rec* A, Rec* B, size_t cap, const uint32_t* begin,
                               const uint32_t* len, uint32_t lower_mask, uint32_t* wcnt,
-                              uint32_t* pack, uint32_t* fold, hipStream_t st) {
-  hipLaunchKernelGGL(k_window, dim3(NL * kWinPerList), dim3(kBlock), 0, st, A, B, cap, begin, len,
-                     lower_mask, wcnt);
-  hipLaunchKernelGGL(k_window_pack, dim3(NL * kWinPerList), dim3(kBlock), 0, st, B, A, cap, len,
-                     wcnt, pack);
-  hipLaunchKernelGGL(k_fold, dim3(NL), dim3(kBlock), 0, st, A, cap, pack, lower_mask, fold);
+                              uint32_t* pack, uint32_t* fold, hipStream_t st, LaunchHook* hk) {
+  hooked(hk, "lg_window", [&] {
+    hipLaunchKernelGGL(k_window, dim3(NL * kWinPerList), dim3(kBlock), 0, st, A, B, cap, begin, len,
+                       lower_mask, wcnt);
+  });
+  hooked(hk, "lg_window_pack", [&] {
+    hipLaunchKernelGGL(k_window_pack, dim3(NL * kWinPerList), dim3(kBlock), 0, st, B, A, cap, len,
+                       wcnt, pack);
+  });
+  hooked(hk, "lg_fold", [&] {
+    hipLaunchKernelGGL(k_fold, dim3(NL), dim3(kBlock), 0, st, A, cap, pack, lower_mask, fold);
+  });
   return hipGetLastError();
 }
 
@@ -1358,16 +1364,24 @@ hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* i
 
 hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t max_in,
                             uint64_t* bot, uint64_t* top, uint32_t* cnt, Rec* lst_lo, Rec* lst_up,
-                            const Octagon* oct, Result* res, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_init, dim3(1024), dim3(kBlock), 0, st, bot, top);
+                            const Octagon* oct, Result* res, hipStream_t st, LaunchHook* hk) {
+  hooked(hk, "lg_col_init", [&] {
+    hipLaunchKernelGGL(k_col_init, dim3(1024), dim3(kBlock), 0, st, bot, top);
+  });
   uint32_t g = (max_in + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_col_scatter, dim3(g), dim3(kBlock), 0, st, in, in_count, bot, top);
-  hipLaunchKernelGGL(k_col_emit<0>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
-                     lst_up, oct, res);
-  hipLaunchKernelGGL(k_col_emit<1>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
-                     lst_up, oct, res);
+  hooked(hk, "lg_col_scatter", [&] {
+    hipLaunchKernelGGL(k_col_scatter, dim3(g), dim3(kBlock), 0, st, in, in_count, bot, top);
+  });
+  hooked(hk, "lg_col_emit", [&] {
+    hipLaunchKernelGGL(k_col_emit<0>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
+                       lst_up, oct, res);
+  });
+  hooked(hk, "lg_col_emit", [&] {
+    hipLaunchKernelGGL(k_col_emit<1>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
+                       lst_up, oct, res);
+  });
   return hipGetLastError();
 }
 
@@ -1379,19 +1393,23 @@ hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t ma
 hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
                              uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
                              uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
-                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st) {
+                             Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st,
+                             LaunchHook* hk) {
   const size_t cap = size_t(kColumns) + 2;
   Rec* Alo = lstA;
   Rec* Aup = lstA + cap;
-  hipError_t e = launch_col_build(in, in_count, max_in, bot, top, colcnt, Alo, Aup, oct, res, st);
+  hipError_t e =
+      launch_col_build(in, in_count, max_in, bot, top, colcnt, Alo, Aup, oct, res, st, hk);
   if (e != hipSuccess) return e;
   // lcount and ucount are adjacent: the two list lengths.
   static_assert(offsetof(Result, ucount) == offsetof(Result, lcount) + 4, "list lengths");
   e = launch_list_chains(2, lstA, lstB, cap, nullptr, &res->lcount, 1u, wcnt, res->pack_cnt,
-                         res->fold_cnt, st);
+                         res->fold_cnt, st, hk);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_large_out, dim3(1), dim3(kBlock), 0, st, Alo, Aup, res, res_idx, host,
-                     host_idx, host_n);
+  hooked(hk, "lg_out", [&] {
+    hipLaunchKernelGGL(k_large_out, dim3(1), dim3(kBlock), 0, st, Alo, Aup, res, res_idx, host,
+                       host_idx, host_n);
+  });
   return hipGetLastError();
 }
 

@@ -87,6 +87,23 @@ SINGLE = {
 }
 
 
+_DESCRIBE = {
+    "uniform": "uniform in [0,1)^2",
+    "normal": "normal mean 0.5 sigma 0.1 per axis, clipped to [0,1)",
+    "annulus": "annulus 0.499-0.5 about (0.5, 0.5), uniform angle, area-uniform radius",
+}
+
+
+def describe(name: str) -> str:
+    """One line saying what a single-set workload is."""
+    kind, n, _ = SINGLE[name]
+    return f"{_DESCRIBE[kind]}, {n} float32 points on the 2^-20 grid"
+
+
+def seed_of(name: str) -> int:
+    return SINGLE[name][2]
+
+
 def single(name: str, n: int | None = None) -> np.ndarray:
     """One of the single-set workloads, optionally at a reduced size n (same
     kind and seed; the first n points of the reduced draw, not of the full one)."""
