@@ -119,6 +119,27 @@ ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_surv
                     size_t ws_bytes, void* stream);
 
 /*
+ * ch_filter_noalloc -- ch_filter for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and outputs as ch_filter, with no
+ * workspace argument. Its scratch is a fixed library-owned device array of
+ * ch_filter_noalloc_scratch_bytes() bytes per device (the ch_filter workspace
+ * for CH_FILTER_NOALLOC_MAX_POINTS points), loaded with the library and held
+ * until the process ends. Nothing is allocated or freed on the call path.
+ *   Arguments as ch_filter (d_xy, d_survivors, d_count, d_label, d_oct,
+ *   stream; caller-owned device buffers).
+ * Returns CH_E_INVALID_ARG for n > CH_FILTER_NOALLOC_MAX_POINTS (and as
+ * ch_filter), CH_E_DEVICE as ch_filter. Every call on one device shares that
+ * device's scratch: calls that overlap on one device (concurrent streams,
+ * several host threads or contexts) race and must be serialised by the
+ * caller; calls in one stream are ordered and safe.
+ */
+#define CH_FILTER_NOALLOC_MAX_POINTS (1u << 22)
+size_t ch_filter_noalloc_scratch_bytes(void);
+ch_status ch_filter_noalloc(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_survivors,
+                            uint32_t* d_count, uint8_t* d_label, ch_octagon* d_oct, void* stream);
+
+/*
  * ch_hull -- the whole path of Alg. 1: filter, then the hull of the survivors
  * on the device. Synchronous with respect to `stream`: returns after the hull
  * is in host memory.

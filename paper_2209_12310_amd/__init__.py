@@ -131,6 +131,20 @@ class Context:
         if st != _capi.CH_OK:
             self._raise(st)
 
+    def filter_noalloc_async(self, xy, survivors, count, labels=None, octagon_dev=None):
+        """ch_filter_noalloc: as filter_async, with the library's fixed
+        device scratch instead of a workspace (at most
+        CH_FILTER_NOALLOC_MAX_POINTS points; nothing is allocated)."""
+        n = _check_points(xy)
+        st = self._lib.ch_filter_noalloc(
+            self._h, ctypes.c_void_p(xy.data_ptr()), n, ctypes.c_void_p(survivors.data_ptr()),
+            ctypes.c_void_p(count.data_ptr()),
+            ctypes.c_void_p(labels.data_ptr()) if labels is not None else None,
+            ctypes.c_void_p(octagon_dev.data_ptr()) if octagon_dev is not None else None,
+            self.stream_handle())
+        if st != _capi.CH_OK:
+            self._raise(st)
+
     def filter(self, xy, labels: bool = False, octagon: bool = False) -> FilterResult:
         torch = _torch()
         n = _check_points(xy)

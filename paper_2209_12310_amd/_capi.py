@@ -25,6 +25,7 @@ CH_E_NOT_FOUND = 10
 CH_COUNT_DOMAIN_ERROR = 0xFFFFFFFF
 CH_COUNT_INVALID = 0xFFFFFFFD
 CH_MAX_POINTS = 0x7FFFFFFF
+CH_FILTER_NOALLOC_MAX_POINTS = 1 << 22
 CH_EXTREMES_FUSED = 0
 CH_EXTREMES_TWO_KERNELS = 1
 
@@ -74,6 +75,8 @@ SIGNATURES = {
     "ch_filter_workspace_bytes": (SZ, [U32]),
     "ch_hull_workspace_bytes": (SZ, [U32]),
     "ch_filter": (I32, [P, P, U32, P, P, P, P, P, SZ, P]),
+    "ch_filter_noalloc_scratch_bytes": (SZ, []),
+    "ch_filter_noalloc": (I32, [P, P, U32, P, P, P, P, P]),
     "ch_hull": (I32, [P, P, U32, P, U32, ctypes.POINTER(U32), P, SZ, P]),
     "ch_gpufilter_workspace_bytes": (SZ, [U32]),
     "ch_hull_queues_workspace_bytes": (SZ, [U32]),

@@ -89,6 +89,14 @@ namespace {
 
 constexpr uint32_t kPinIdx = 16384;  // hull indices the device writes to pinned host memory
 
+// Library-owned scratch of ch_filter_noalloc: the ch_filter workspace for
+// CH_FILTER_NOALLOC_MAX_POINTS points, one copy per device, loaded with the
+// code object and held until the process ends. Host code never uses this
+// name as an address: ch_ctx_create looks up the device address with the
+// context's device current and keeps it in the context.
+constexpr size_t kNoAllocBytes = layout(CH_FILTER_NOALLOC_MAX_POINTS).filter_end;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 struct KStat {
   const char* name;
   uint64_t launches;
@@ -106,6 +114,7 @@ struct ch_ctx {
   uint32_t narrow_blocks = 256;
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   unsigned char* pinned_dev = nullptr;  // its device address (null: copied, not written directly)
+  void* noalloc_ws = nullptr;           // device address of `scratch` on this context's device
   std::string err;
   ch_hull_info last{};  // counts of the last successful ch_hull
   // Batch-mode parameters: fixed ones (ch_batch_params_set), else the tuned
@@ -532,6 +541,17 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
     if (hipHostGetDevicePointer(&dp, ctx->pinned, 0) == hipSuccess) ctx->pinned_dev = static_cast<unsigned char*>(dp);
     else (void)hipGetLastError();
   }
+  {
+    // The no-allocation filter's scratch on this device (device current).
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+      (void)hipGetLastError();
+      (void)hipHostFree(ctx->pinned);
+      delete ctx;
+      return CH_E_DEVICE;
+    }
+    ctx->noalloc_ws = sp;
+  }
   ctx->batch = default_batch_params(ctx->cu_count);
   {
     hipDeviceProp_t prop;
@@ -565,6 +585,8 @@ const char* ch_last_error(const ch_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 size_t ch_filter_workspace_bytes(uint32_t n) { return layout(n).filter_end; }
 size_t ch_hull_workspace_bytes(uint32_t n) { return layout(n).total; }
 
+size_t ch_filter_noalloc_scratch_bytes(void) { return kNoAllocBytes; }
+
 ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_survivors,
                     uint32_t* d_count, uint8_t* d_label, ch_octagon* d_oct, void* d_ws,
                     size_t ws_bytes, void* stream) {
@@ -593,6 +615,20 @@ ch_status ch_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_surv
   }
   prof_collect(ctx, st);
   return CH_OK;
+}
+
+ch_status ch_filter_noalloc(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* d_survivors,
+                            uint32_t* d_count, uint8_t* d_label, ch_octagon* d_oct, void* stream) {
+  if (!ctx) return CH_E_INVALID_ARG;
+  if (n > CH_FILTER_NOALLOC_MAX_POINTS)
+    return fail(ctx, CH_E_INVALID_ARG,
+                "ch_filter_noalloc takes at most %u points (its scratch is fixed), got %u",
+                (unsigned)CH_FILTER_NOALLOC_MAX_POINTS, n);
+  if (!ctx->noalloc_ws) return fail(ctx, CH_E_DEVICE, "no device scratch on this context");
+  // Same kernels as ch_filter; every per-call counter in the scratch is reset
+  // by the kernels of the call itself, so no clearing is needed here.
+  return ch_filter(ctx, d_xy, n, d_survivors, d_count, d_label, d_oct, ctx->noalloc_ws,
+                   kNoAllocBytes, stream);
 }
 
 ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_idx, uint32_t cap,

@@ -120,3 +120,25 @@ def test_serve_null_arguments(lib):
     assert lib.ch_serve_submit(None, None, 0, ctypes.byref(t)) == 1
     assert lib.ch_serve_stats(None, None, None, None, None, None) == 1
     assert lib.ch_serve_stop(None) == 1
+
+
+def test_noalloc_scratch_is_the_filter_workspace_at_its_limit(lib):
+    """ch_filter_noalloc's fixed scratch is exactly ch_filter's workspace for
+    CH_FILTER_NOALLOC_MAX_POINTS points, and modest (under 32 MiB)."""
+    sb = lib.ch_filter_noalloc_scratch_bytes
+    sb.restype = ctypes.c_size_t
+    sb.argtypes = []
+    f = lib.ch_filter_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_uint32]
+    assert sb() == f(_capi.CH_FILTER_NOALLOC_MAX_POINTS)
+    assert sb() < 32 << 20
+    text = open(HEADER).read()
+    assert f"#define CH_FILTER_NOALLOC_MAX_POINTS (1u << {_capi.CH_FILTER_NOALLOC_MAX_POINTS.bit_length() - 1})" in text
+
+
+def test_noalloc_rejects_null_context(lib):
+    fn = lib.ch_filter_noalloc
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32] + [ctypes.c_void_p] * 5
+    assert fn(None, None, 0, None, None, None, None, None) == _capi.CH_E_INVALID_ARG
