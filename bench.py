@@ -60,8 +60,10 @@ def kernel_alg_bytes(name: str, n: int, info: dict):
         "reduce8": 8 * n,                         # pass 1
         "filter_compact": 8 * n + 16 * surv,      # pass 2 + survivor records
         "cand_filter": 16 * cand + 16 * surv,     # candidate records in, survivors out
-        "lg_col_init": 2 * 8 * (1 << 20),         # two 2^20-entry column tables cleared
-        "lg_col_scatter": 16 * surv,              # survivor records read (atomics into the tables)
+        # large-hull path (input: the survivor records when no tile round ran)
+        "lg_count": 16 * surv,                    # records read, chunk counts in LDS
+        "lg_scatter": 32 * surv,                  # records read and written to their chunk
+        "lg_chunk": 16 * surv,                    # records read, column table and chains in LDS
     }
     return model.get(name)
 
@@ -325,7 +327,7 @@ def pct(vals, q):
     return float(np.percentile(np.asarray(vals, dtype=np.float64), q))
 
 
-def bench_batch(ctx, steps: int, warmup: int) -> dict:
+def bench_batch(ctx, steps: int, warmup: int, params=None, plain_mode: bool = True) -> dict:
     """Batched mode on 4096 sets (log-uniform sizes in [1e3, 1e6], kinds
     uniform / normal / annulus 0.49-0.5, seed 3): parameters from the
     autotuner, then the ch_hull_batch call captured once in a HIP graph and
@@ -347,9 +349,13 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
     idx = torch.empty(n, dtype=torch.int32, device="cuda:0")
     cnt = torch.empty(nsets, dtype=torch.int32, device="cuda:0")
     ws = ctx.workspace(ctx._lib.ch_hull_batch_workspace_bytes(nsets, n))
-    log("tuning batch parameters")
     t0 = time.perf_counter()
-    params = ctx.tune_batch(t, o, idx, cnt, ws)
+    if params is None:
+        log("tuning batch parameters")
+        params = ctx.tune_batch(t, o, idx, cnt, ws)
+    else:
+        log(f"batch parameters fixed: {params}")
+        ctx.set_batch_params(params)
     tune_s = time.perf_counter() - t0
     for _ in range(warmup):
         ctx.hull_batch_async(t, o, idx, cnt, ws)
@@ -410,15 +416,17 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
                 "mean_us": round(pass_ms * 1e3, 2),
                 "note": "8 B per point read; candidate records written are left out (lower bound)"}
     # Plain mode: one synchronous ch_hull per set.
-    log("plain mode: one ch_hull per set")
-    for s in range(min(64, nsets)):
-        ctx.hull(t[int(off[s]): int(off[s + 1])])
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    for s in range(nsets):
-        ctx.hull(t[int(off[s]): int(off[s + 1])])
-    torch.cuda.synchronize()
-    plain = time.perf_counter() - tp
+    plain = float("nan")
+    if plain_mode:
+        log("plain mode: one ch_hull per set")
+        for s in range(min(64, nsets)):
+            ctx.hull(t[int(off[s]): int(off[s + 1])])
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for s in range(nsets):
+            ctx.hull(t[int(off[s]): int(off[s + 1])])
+        torch.cuda.synchronize()
+        plain = time.perf_counter() - tp
     ms = float(np.mean(lat))
     return {"workload": "batch_4096", "sets": nsets, "points": n, "steps": steps,
             "timing": "one HIP graph replay of the captured ch_hull_batch call per step",
@@ -429,8 +437,9 @@ def bench_batch(ctx, steps: int, warmup: int) -> dict:
             "batch_latency_p50_ms": round(pct(lat, 50), 3), "batch_latency_p99_ms": round(pct(lat, 99), 3),
             "eager_ms_per_batch": round(float(np.mean(lat_eager)), 3),
             "eager_wall_ms_per_batch": round(wall_eager * 1e3, 3),
-            "plain_ms": round(plain * 1e3, 1), "plain_hulls_per_s": round(nsets / plain, 1),
-            "speedup_vs_plain": round(plain / (ms * 1e-3), 2),
+            "plain_ms": round(plain * 1e3, 1) if plain_mode else None,
+            "plain_hulls_per_s": round(nsets / plain, 1) if plain_mode else None,
+            "speedup_vs_plain": round(plain / (ms * 1e-3), 2) if plain_mode else None,
             "params": params, "tune_s": round(tune_s, 2), "kernels": kernels, "roofline": roof,
             "kinds": {k: kinds.count(k) for k in sorted(set(kinds))}}
 
@@ -583,6 +592,9 @@ def main() -> int:
                     help="single-set workload of the headline line (profiling runs of other configs)")
     ap.add_argument("--only-batch", action="store_true",
                     help="measure batch mode alone (profiling runs of batch_4096)")
+    ap.add_argument("--batch-params", default=None,
+                    help="JSON batch parameters to use instead of tuning (profiling runs)")
+    ap.add_argument("--no-plain", action="store_true", help="skip batch plain mode (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -596,7 +608,9 @@ def main() -> int:
 
         import paper_2209_12310_amd as ch
         ctx = ch.Context(0)
-        print(json.dumps({"batch": bench_batch(ctx, max(5, min(args.steps, 20)), args.warmup)}), flush=True)
+        bp = json.loads(args.batch_params) if args.batch_params else None
+        print(json.dumps({"batch": bench_batch(ctx, max(5, min(args.steps, 20)), args.warmup, bp,
+                                               not args.no_plain)}), flush=True)
         ctx.close()
         return 0
     workload = args.workload

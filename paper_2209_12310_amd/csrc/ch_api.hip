@@ -48,8 +48,8 @@ hipError_t launch_hull_final(const Rec* in_rec, const uint32_t* in_count, Result
 hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* in_count,
                              Rec* out_rec, uint32_t* out_count, uint32_t* tile_ctr,
                              hipStream_t st);
-hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
-                             uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
+hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in, Rec* part,
+                             uint32_t* phist, uint32_t* ptot, Rec* lstA, Rec* lstB,
                              uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
                              Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st,
                              LaunchHook* hk);
@@ -112,6 +112,8 @@ struct ch_ctx {
   uint32_t filter_max_blocks = 1024;
   uint32_t fused_max_blocks = 512;
   uint32_t narrow_blocks = 256;
+  uint32_t large_direct = kLargeDirect;  // survivors from which ch_hull skips the tile rounds
+  bool poll = true;  // watch the published status instead of waiting for the stream
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   unsigned char* pinned_dev = nullptr;  // its device address (null: copied, not written directly)
   void* noalloc_ws = nullptr;           // device address of `scratch` on this context's device
@@ -530,6 +532,11 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1 && v <= kReduceMaxBlocks) ctx->narrow_blocks = (uint32_t)v;
   }
+  if (const char* e = std::getenv("CH_HULL_WAIT")) ctx->poll = std::strcmp(e, "stream") != 0;
+  if (const char* e = std::getenv("CH_LARGE_DIRECT")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= kFinalTile && v <= (long)CH_MAX_POINTS) ctx->large_direct = (uint32_t)v;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), kResBytes + 4 * kPinIdx,
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete ctx;
@@ -676,14 +683,36 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     if (!ctx->pinned_dev) return fetch();
     return hipStreamSynchronize(st);
   };
+  // The block hull publishes its result block with the status word last
+  // (system-scope release): mark it pending before the launch, then watch
+  // it instead of waiting for the stream (a stream wait adds its own wake-up
+  // latency). A stream that ends with the status still pending is reported
+  // by the status check that follows.
+  Result* hres_w = reinterpret_cast<Result*>(ctx->pinned);
+  auto arm_final = [&]() {
+    if (ctx->pinned_dev) __atomic_store_n(&hres_w->status, (uint32_t)RES_PENDING, __ATOMIC_RELEASE);
+  };
+  auto wait_final = [&]() -> hipError_t {
+    if (!ctx->pinned_dev || ctx->prof || !ctx->poll) return fetch_final();
+    for (uint32_t spins = 1;; ++spins) {
+      if (__atomic_load_n(&hres_w->status, __ATOMIC_ACQUIRE) != RES_PENDING) return hipSuccess;
+      if ((spins & 1023u) == 0) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q == hipSuccess) return hipSuccess;
+        if (q != hipErrorNotReady) return q;
+      }
+      __builtin_ia32_pause();
+    }
+  };
 
   hipError_t e;
+  arm_final();
   {
     ProfScope p(ctx, st, "hull_final");
     e = launch_hull_final(srec, &hdr->count, res, res_idx, &hdr->oct, dres_host, didx_host, pin_n, st);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
-  if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "hull final");
+  if ((e = wait_final()) != hipSuccess) return hip_fail(ctx, e, "hull final");
   prof_collect(ctx, st);
   if (hres->status == RES_DOMAIN) return fail(ctx, CH_E_DOMAIN, "input outside the 2^-20 grid");
   ch_hull_info info{};
@@ -694,9 +723,12 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   bool large = false;
   int round = 0;
   int last_list = -1;  // record list holding the latest round's output (-1: the survivors)
+  // The survivors: the octagon test's output, or the candidate records
+  // themselves (list B) when the test was skipped.
+  const Rec* surv0 = hres->cand_surv ? rec[1] : srec;
   // Many survivors (points near a smooth boundary keep about half of every
   // tile hull): straight to the large-hull path.
-  if (hres->status == RES_MORE && hres->cin > kLargeDirect) large = true;
+  if (hres->status == RES_MORE && hres->cin > ctx->large_direct) large = true;
   while (!large && hres->status != RES_DONE) {
     if (hres->status != RES_MORE) return fail(ctx, CH_E_DEVICE, "hull status %u", hres->status);
     const uint32_t cin = hres->cin;
@@ -707,17 +739,18 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     const uint32_t* in_count = round == 0 ? &hdr->count : &res->round_cnt[round];
     {
       ProfScope p(ctx, st, round == 0 ? "hull_round0" : "hull_round");
-      e = launch_hull_round(grid, round ? rec[(round - 1) & 1] : srec, in_count, rec[round & 1],
+      e = launch_hull_round(grid, round ? rec[(round - 1) & 1] : surv0, in_count, rec[round & 1],
                             &res->round_cnt[round + 1], &res->round_tile[round], st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "hull round launch");
+    arm_final();
     {
       ProfScope p(ctx, st, "hull_final");
       e = launch_hull_final(rec[round & 1], &res->round_cnt[round + 1], res, res_idx, &hdr->oct,
                             dres_host, didx_host, pin_n, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
-    if ((e = fetch_final()) != hipSuccess) return hip_fail(ctx, e, "hull round");
+    if ((e = wait_final()) != hipSuccess) return hip_fail(ctx, e, "hull round");
     prof_collect(ctx, st);
     last_list = round & 1;
     ++round;
@@ -734,13 +767,15 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   if (large) {
     // input: the last round's output, or the survivors when no round ran
     const uint32_t cin = round ? hres->round_cnt[round] : hres->cin;
-    const Rec* lin = round ? rec[last_list] : srec;
+    const Rec* lin = round ? rec[last_list] : surv0;
     const uint32_t* lcnt = round ? &res->round_cnt[round] : &hdr->count;
     {
       // Per-kernel events of the large-hull path when profiling is on.
       ProfHook hook(ctx, st);
-      e = launch_large_path(lin, lcnt, cin, at<uint64_t>(d_ws, L.colbot), at<uint64_t>(d_ws, L.coltop),
-                            at<uint32_t>(d_ws, L.colcnt), at<Rec>(d_ws, L.lstA),
+      // The partition goes to a record list the input does not occupy.
+      Rec* part = lin == srec ? rec[0] : (lin == rec[0] ? srec : rec[0]);
+      e = launch_large_path(lin, lcnt, cin, part, at<uint32_t>(d_ws, L.phist),
+                            at<uint32_t>(d_ws, L.ptot), at<Rec>(d_ws, L.lstA),
                             at<Rec>(d_ws, L.lstB), at<uint32_t>(d_ws, L.wcnt), &hdr->oct, res,
                             res_idx, dres_host, didx_host, pin_n, st, ctx->prof ? &hook : nullptr);
     }

@@ -251,6 +251,7 @@ __device__ void reset_call_state(Header* hdr, Result* res, bool count) {
     res->h = 0;
     res->lcount = res->ucount = 0;
     res->ncand = 0;
+    res->cand_surv = 0;
   }
   for (int r = lane; r < kMaxRounds; r += 64) { res->round_cnt[r] = 0; res->round_tile[r] = 0; }
   if (lane < 2) { res->pack_cnt[lane] = 0; res->fold_cnt[lane] = 0; }
@@ -637,8 +638,17 @@ struct StageCap<Rec> {
 
 // Exact-test queue of the hull path: points that pass neither cheap test
 // wait in LDS until a whole wave's worth (64) can be tested together, so the
-// exact tests run with full waves however rare those points are.
+// exact tests run with full waves however rare those points are. The fused
+// pass of a single set (queue kQueueF) appends a whole batch's points with
+// one wave sync when they fit.
 constexpr int kQueue = 128;
+constexpr int kQueueF = 256;
+
+// The candidates' octagon test is skipped when it removes fewer than 1 in
+// kSkipRatio of the first kSkipEst candidate records.
+constexpr uint32_t kSkipEst = 1024;
+constexpr uint32_t kSkipRatio = 8;
+constexpr uint32_t kSkipMin = 1u << 17;  // candidates from which the estimate runs (> kFinalTile)
 
 template <bool LABELS, class P>
 __global__ __launch_bounds__(kBlock) void k_filter(const float* __restrict__ xy, uint32_t n,
@@ -937,6 +947,38 @@ __global__ __launch_bounds__(kBlock) void k_filter_hull(const float* __restrict_
   // After a fused pass with a usable sample polygon only its candidates need
   // the octagon test; otherwise this is the second read of the points.
   if (use_cand) {
+    // Many candidates that the octagon barely thins (points near a smooth
+    // curve, whose sample polygon already holds most of the octagon): the
+    // test is skipped and the candidate records are the survivors. Every
+    // workgroup estimates on the same first records, so all decide alike;
+    // only when the hull path will not read the survivor records (more than
+    // one block of them) -- the hull is the same either way, the candidates
+    // containing every hull vertex.
+    const uint32_t m = *cand_count;
+    if (m >= kSkipMin && s_oct.status == 0) {
+      __shared__ uint32_t s_rm[kWaves];
+      uint32_t rm = 0;
+#pragma unroll
+      for (uint32_t e = 0; e < kSkipEst / kBlock; ++e) {
+        const Rec r = cand[threadIdx.x + e * kBlock];
+        rm += classify<false>((float)r.x * (1.0f / kGridF), (float)r.y * (1.0f / kGridF), r.i, &s_oct,
+                              s_vidx).keep ? 0u : 1u;
+      }
+      rm = wave_allreduce(rm, [](uint32_t a, uint32_t b) { return a + b; });
+      if ((threadIdx.x & 63) == 0) s_rm[threadIdx.x >> 6] = rm;
+      __syncthreads();
+      uint32_t removed = 0;
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) removed += s_rm[i];
+      if (removed * kSkipRatio < kSkipEst) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          *ncand_out = m;
+          *count_out = m;
+          res->cand_surv = 1;
+        }
+        return;
+      }
+    }
     cand_filter(cand, cand_count, &s_oct, s_vidx, surv, count_out, ncand_out);
     return;
   }
@@ -1085,8 +1127,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
   __shared__ Rec s_buf[kWaves][kCapW];
   __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ uint32_t s_lut[kLutBins];
-  __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
-  __shared__ uint32_t s_qg[kWaves][kQueue];
+  __shared__ float s_qx[kWaves][kQueueF], s_qy[kWaves][kQueueF];
+  __shared__ uint32_t s_qg[kWaves][kQueueF];
   __shared__ uint32_t s_bad;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -1276,11 +1318,41 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
           any |= mk[2 * u] | mk[2 * u + 1];
         }
         if (any) {
+          uint32_t tot = 0;
 #pragma unroll
-          for (int u = 0; u < kUF; ++u) {
-            const uint32_t g = head + 2 * (b * per_batch + u * 64 + lane);
-            push(mk[2 * u], cur[u].x, cur[u].y, g);
-            push(mk[2 * u + 1], cur[u].z, cur[u].w, g + 1);
+          for (int j = 0; j < 2 * kUF; ++j) tot += popc64(mk[j]);
+          if (qn + tot <= (uint32_t)kQueueF) {
+            // The whole batch's outside points join the queue at once (one
+            // wave sync), then full waves of them are drained.
+            uint32_t pos = qn;
+#pragma unroll
+            for (int u = 0; u < kUF; ++u) {
+              const uint32_t g = head + 2 * (b * per_batch + u * 64 + lane);
+              const uint64_t m0 = mk[2 * u], m1 = mk[2 * u + 1];
+              if ((m0 >> lane) & 1ull) {
+                const uint32_t p0 = pos + popc64(m0 & lt);
+                s_qx[w][p0] = cur[u].x; s_qy[w][p0] = cur[u].y; s_qg[w][p0] = g;
+              }
+              pos += popc64(m0);
+              if ((m1 >> lane) & 1ull) {
+                const uint32_t p1 = pos + popc64(m1 & lt);
+                s_qx[w][p1] = cur[u].z; s_qy[w][p1] = cur[u].w; s_qg[w][p1] = g + 1;
+              }
+              pos += popc64(m1);
+            }
+            qn = pos;
+            wave_sync();
+            while (qn >= 64) {
+              qn -= 64;
+              drain(qn, 64);
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < kUF; ++u) {
+              const uint32_t g = head + 2 * (b * per_batch + u * 64 + lane);
+              push(mk[2 * u], cur[u].x, cur[u].y, g);
+              push(mk[2 * u + 1], cur[u].z, cur[u].w, g + 1);
+            }
           }
         }
       }

@@ -52,6 +52,50 @@ __device__ int seg_chain(const int32_t* sx, const int32_t* sy, const uint32_t* s
   return top;
 }
 
+// Exact pre-sieve of an x-sorted list of distinct points before its chain.
+// For such a list, p_i is a strict vertex of the lower chain exactly when
+// orient(p_a, p_i, p_b) > 0 for every a < i < b (the upper chain mirrors the
+// sign), so p_i can go as soon as one pair fails; the chain of what is left
+// is the same, since no vertex ever fails a pair. Every inner point tests the
+// pairs (i - k, i + k) for a few spreads k (clamped to the list), all points
+// at once; the survivors are compacted in place (order kept) and their
+// count returned. Whole workgroup; MAXE >= ceil(u / kBlock).
+template <bool LOWER, int MAXE>
+__device__ uint32_t presieve(int32_t* px, int32_t* py, uint32_t* pi, uint32_t u) {
+  if (u <= 64) return u;  // (u is uniform: every thread returns here or none)
+  constexpr int kSpreads = 8;
+  constexpr uint32_t spread[kSpreads] = {1, 2, 4, 7, 12, 20, 33, 54};
+  const uint32_t E = (u + kBlock - 1) / kBlock;
+  const uint32_t i0 = threadIdx.x * E;
+  int32_t x[MAXE], y[MAXE];
+  uint32_t id[MAXE], keep = 0, nk = 0;
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const uint32_t i = i0 + (uint32_t)e;
+    if ((uint32_t)e < E && i < u) {
+      x[e] = px[i]; y[e] = py[i]; id[e] = pi[i];
+      bool k = true;
+      if (i > 0 && i + 1 < u) {
+#pragma unroll
+        for (int s = 0; s < kSpreads; ++s) {
+          const uint32_t a = i >= spread[s] ? i - spread[s] : 0u;
+          const uint32_t b = i + spread[s] < u ? i + spread[s] : u - 1;
+          k &= !bad_turn<LOWER>(px[a], py[a], x[e], y[e], px[b], py[b]);
+        }
+      }
+      if (k) { keep |= 1u << e; ++nk; }
+    }
+  }
+  uint32_t total;
+  uint32_t pos = block_excl_scan(nk, total);  // its barriers end every read above
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    if (keep & (1u << e)) { px[pos] = x[e]; py[pos] = y[e]; pi[pos] = id[e]; ++pos; }
+  }
+  __syncthreads();
+  return total;
+}
+
 // One side's chain of u x-sorted distinct points (src), written to dst[0..len):
 // per-thread segment chains, then pairwise merges up a binary tree. MAXC
 // bounds the elements one thread moves per merge (ceil(S/2), S = u/256).
@@ -137,6 +181,8 @@ __device__ void dual_chain(int32_t* px, int32_t* py, uint32_t* pi, uint32_t ul, 
                            int32_t* uy, uint32_t* ui, uint32_t uu, uint16_t* cnt_l,
                            uint16_t* cnt_u, int32_t* wij_l, int32_t* wij_u, uint32_t& nl,
                            uint32_t& nu) {
+  ul = presieve<true, 2 * MAXC>(px, py, pi, ul);
+  uu = presieve<false, 2 * MAXC>(ux, uy, ui, uu);
   constexpr uint32_t kMinSeg = 2 * MAXC < 8 ? 2 * MAXC : 8;
   uint32_t SL = (ul + kBlock - 1) / kBlock, SU = (uu + kBlock - 1) / kBlock;
   if (SL < kMinSeg) SL = kMinSeg;
@@ -738,16 +784,25 @@ __device__ __forceinline__ Rec hull_elem(const HullSmem<T>& sm, uint32_t k, uint
 // The result block for the host, written straight into pinned host memory
 // mapped for the device (no copy launch): the device Result with this
 // call's status, h and input count.
+// The status word goes last, after a system-scope fence of every thread
+// (this workgroup's earlier writes to host memory, the hull indices
+// included, are visible first): the host may read the block as soon as it
+// sees the status change. Whole workgroup.
 __device__ void publish_result(const Result* __restrict__ res, Result* __restrict__ host,
                                uint32_t status, uint32_t h, uint32_t cin) {
   constexpr uint32_t kWords = sizeof(Result) / 4;
+  constexpr uint32_t kStatus = offsetof(Result, status) / 4;
   for (uint32_t t = threadIdx.x; t < kWords; t += kBlock) {
+    if (t == kStatus) continue;
     uint32_t v = reinterpret_cast<const uint32_t*>(res)[t];
-    if (t == offsetof(Result, status) / 4) v = status;
-    else if (t == offsetof(Result, h) / 4) v = h;
+    if (t == offsetof(Result, h) / 4) v = h;
     else if (t == offsetof(Result, cin) / 4) v = cin;
     reinterpret_cast<uint32_t*>(host)[t] = v;
   }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&host->status, status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // One workgroup: the hull of all candidates when they fit (status DONE),
@@ -819,27 +874,6 @@ __global__ __launch_bounds__(kBlock) void k_hull_round(const Rec* __restrict__ i
 
 // ------------------------------------------------------ large-hull path
 
-__global__ void k_col_init(uint64_t* __restrict__ bot, uint64_t* __restrict__ top) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t x = g; x < kColumns; x += gridDim.x * blockDim.x) {
-    bot[x] = ~0ull;
-    top[x] = 0ull;
-  }
-}
-
-// Per column: bottom = min (y, index), top = max (y, -index). An empty top
-// column reads 0 (y is stored plus one).
-__global__ void k_col_scatter(const Rec* __restrict__ in, const uint32_t* __restrict__ in_count,
-                              uint64_t* __restrict__ bot, uint64_t* __restrict__ top) {
-  const uint32_t c = *in_count;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < c; k += gridDim.x * blockDim.x) {
-    const Rec r = in[k];
-    atomicMin((unsigned long long*)&bot[r.x], ((unsigned long long)(uint32_t)r.y << 32) | r.i);
-    atomicMax((unsigned long long*)&top[r.x],
-              ((unsigned long long)(uint32_t)(r.y + 1) << 32) | (0xFFFFFFFFu - r.i));
-  }
-}
-
 __device__ __forceinline__ Rec bot_rec(uint32_t x, uint64_t b) {
   Rec r;
   r.x = (int32_t)x; r.y = (int32_t)(b >> 32); r.i = (uint32_t)b; r.pad = 0;
@@ -851,63 +885,245 @@ __device__ __forceinline__ Rec top_rec(uint32_t x, uint64_t t) {
   return r;
 }
 
-// Emission rule per occupied column x: lower list gets bottom(x), plus top(x)
-// after it when x is the last column and top != bottom; upper list gets
-// top(x), preceded by bottom(x) when x is the first column and top != bottom.
-// PASS 0 counts per chunk, PASS 1 writes in column order.
-template <int PASS>
-__global__ __launch_bounds__(kBlock) void k_col_emit(const uint64_t* __restrict__ bot,
-                                                     const uint64_t* __restrict__ top,
-                                                     uint32_t* __restrict__ cnt,
-                                                     Rec* __restrict__ lst_lo,
-                                                     Rec* __restrict__ lst_up,
+// Large-hull path. Only the lowest and the highest point of a grid column can
+// be a strict hull vertex (the lexicographic ends aside), so the records are
+// reduced per column and read in x order -- two x-sorted lists, the lower and
+// the upper one, with no sort. The records are first partitioned by chunk of
+// kChunkCols columns (counts per workgroup in LDS, a scan per chunk, then a
+// scatter through LDS cursors); one workgroup per chunk then keeps the bottom
+// and top point of each of its columns with LDS atomics and builds the
+// chunk's two chains in LDS. No global atomics are involved.
+//
+// Emission rule per occupied column x: the lower list gets bottom(x), plus
+// top(x) after it when x is the last column (xmax) and top != bottom; the
+// upper list gets top(x), preceded by bottom(x) when x is the first column
+// (xmin) and top != bottom. Andrew's chains run from the lexicographic
+// minimum (bottom of xmin) to the maximum (top of xmax).
+
+// Partition slice of workgroup g of G: records [g * per, min((g+1) * per, c)).
+__device__ __forceinline__ void part_slice(uint32_t c, uint32_t& a, uint32_t& b) {
+  const uint32_t per = (c + gridDim.x - 1) / gridDim.x;
+  a = blockIdx.x * per;
+  b = a + per < c ? a + per : c;
+  if (a > c) a = c;
+}
+
+__device__ __forceinline__ uint32_t chunk_of(int32_t x) { return (uint32_t)x / kChunkCols; }
+
+// Counts of the slice's records per chunk: hist[k * G + g].
+__global__ __launch_bounds__(kBlock) void k_lg_count(const Rec* __restrict__ in,
+                                                     const uint32_t* __restrict__ in_count,
+                                                     uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[kChunks];
+  for (uint32_t k = threadIdx.x; k < kChunks; k += kBlock) s_h[k] = 0;
+  __syncthreads();
+  uint32_t a, b;
+  part_slice(*in_count, a, b);
+  constexpr uint32_t kLd = 4;  // loads in flight per thread
+  for (uint32_t i0 = a; i0 < b; i0 += kLd * kBlock) {
+    int32_t x[kLd];
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v) {
+      const uint32_t i = i0 + v * kBlock + threadIdx.x;
+      x[v] = in[i < b ? i : b - 1].x;
+    }
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v)
+      if (i0 + v * kBlock + threadIdx.x < b) atomicAdd(&s_h[chunk_of(x[v])], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < kChunks; k += kBlock) hist[k * gridDim.x + blockIdx.x] = s_h[k];
+}
+
+// One workgroup per chunk k: exclusive scan of hist[k * G .. k * G + G) in
+// place, the chunk's total to tot[k].
+__global__ __launch_bounds__(kBlock) void k_lg_scan(uint32_t* __restrict__ hist, uint32_t G,
+                                                    uint32_t* __restrict__ tot) {
+  constexpr uint32_t E = kPartMax / kBlock;
+  uint32_t* row = hist + blockIdx.x * G;
+  uint32_t v[E], sum = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    const uint32_t j = threadIdx.x * E + e;
+    v[e] = j < G ? row[j] : 0u;
+    sum += v[e];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, total);
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    const uint32_t j = threadIdx.x * E + e;
+    if (j < G) row[j] = run;
+    run += v[e];
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// First record of every chunk: exclusive scan of the chunk totals into s_base.
+__device__ __forceinline__ void chunk_bases(const uint32_t* __restrict__ tot, uint32_t* s_base) {
+  static_assert(kChunks == 2 * kBlock, "two chunks per thread");
+  const uint32_t t0 = tot[2 * threadIdx.x], t1 = tot[2 * threadIdx.x + 1];
+  uint32_t all;
+  const uint32_t e = block_excl_scan(t0 + t1, all);
+  s_base[2 * threadIdx.x] = e;
+  s_base[2 * threadIdx.x + 1] = e + t0;
+  if (threadIdx.x == 0) s_base[kChunks] = all;
+  __syncthreads();
+}
+
+// The slice's records to their chunk's range (order within a chunk is
+// immaterial: the column reduction does not depend on it).
+__global__ __launch_bounds__(kBlock) void k_lg_scatter(const Rec* __restrict__ in,
+                                                       const uint32_t* __restrict__ in_count,
+                                                       const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ tot,
+                                                       Rec* __restrict__ out) {
+  __shared__ uint32_t s_cur[kChunks + 1];
+  chunk_bases(tot, s_cur);
+  for (uint32_t k = threadIdx.x; k < kChunks; k += kBlock) s_cur[k] += hist[k * gridDim.x + blockIdx.x];
+  __syncthreads();
+  uint32_t a, b;
+  part_slice(*in_count, a, b);
+  constexpr uint32_t kLd = 4;  // loads in flight per thread
+  for (uint32_t i0 = a; i0 < b; i0 += kLd * kBlock) {
+    Rec r[kLd];
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v) {
+      const uint32_t i = i0 + v * kBlock + threadIdx.x;
+      r[v] = in[i < b ? i : b - 1];
+    }
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v)
+      if (i0 + v * kBlock + threadIdx.x < b) out[atomicAdd(&s_cur[chunk_of(r[v].x)], 1u)] = r[v];
+  }
+}
+
+constexpr uint32_t kChunkList = kChunkCols + 1;  // records of a chunk's list at most
+constexpr int kChunkMaxc = ((kChunkList + kBlock - 1) / kBlock + 1) / 2;
+
+struct ChunkSmem {
+  union {
+    struct { uint64_t bot[kChunkCols], top[kChunkCols]; } t;  // column table
+    struct {                                                  // the two lists, then chains
+      int32_t lx[kChunkList], ly[kChunkList];
+      uint32_t li[kChunkList];
+      int32_t ux[kChunkList], uy[kChunkList];
+      uint32_t ui[kChunkList];
+    } l;
+  } u;
+  uint16_t cnt_l[kBlock], cnt_u[kBlock];
+  int32_t wij_l[kBlock], wij_u[kBlock];
+  uint32_t base[kChunks + 1];
+};
+
+// One workgroup per chunk: its records' bottom and top per column, the lower
+// and upper lists in x order, their chains; chain k of list q goes to
+// dst + q * cap + k * kChunkStride, its length to wcnt[q * kChunks + k].
+__global__ __launch_bounds__(kBlock) void k_lg_chunk(const Rec* __restrict__ part,
+                                                     const uint32_t* __restrict__ tot,
                                                      const Octagon* __restrict__ oct,
-                                                     Result* __restrict__ res) {
-  constexpr uint32_t PER = kColChunk / kBlock;  // 16 columns per thread
-  const uint32_t xmin = (uint32_t)oct->vx[4], xmax = (uint32_t)oct->vx[0];
-  const uint32_t x0 = blockIdx.x * kColChunk + threadIdx.x * PER;
+                                                     Rec* __restrict__ dst, size_t cap,
+                                                     uint32_t* __restrict__ wcnt) {
+  __shared__ ChunkSmem sm;
+  constexpr uint32_t PER = kChunkCols / kBlock;  // columns per thread
+  const uint32_t k = blockIdx.x;
+  chunk_bases(tot, sm.base);
+  const uint32_t r0 = sm.base[k], r1 = sm.base[k + 1];
+  if (r0 == r1) {
+    if (threadIdx.x == 0) { wcnt[k] = 0; wcnt[kChunks + k] = 0; }
+    return;
+  }
+  for (uint32_t c = threadIdx.x; c < kChunkCols; c += kBlock) {
+    sm.u.t.bot[c] = ~0ull;
+    sm.u.t.top[c] = 0ull;
+  }
+  __syncthreads();
+  const int32_t x0 = (int32_t)(k * kChunkCols);
+  constexpr uint32_t kLd = 4;  // loads in flight per thread
+  for (uint32_t i0 = r0; i0 < r1; i0 += kLd * kBlock) {
+    Rec q[kLd];
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v) {
+      const uint32_t i = i0 + v * kBlock + threadIdx.x;
+      q[v] = part[i < r1 ? i : r1 - 1];
+    }
+#pragma unroll
+    for (uint32_t v = 0; v < kLd; ++v) {
+      if (i0 + v * kBlock + threadIdx.x >= r1) continue;
+      const uint32_t c = (uint32_t)(q[v].x - x0);
+      atomicMin(&sm.u.t.bot[c], ((unsigned long long)(uint32_t)q[v].y << 32) | q[v].i);
+      atomicMax(&sm.u.t.top[c],
+                ((unsigned long long)(uint32_t)(q[v].y + 1) << 32) | (0xFFFFFFFFu - q[v].i));
+    }
+  }
+  __syncthreads();
+  // Thread t owns columns [PER t, PER (t + 1)): read them, then (the lists
+  // overwrite the table) place its list entries.
+  const int32_t xmin = oct->vx[4], xmax = oct->vx[0];
+  uint64_t cb[PER], ct[PER];
   uint32_t nlo = 0, nup = 0;
+#pragma unroll
   for (uint32_t e = 0; e < PER; ++e) {
-    const uint32_t x = x0 + e;
-    const uint64_t b = bot[x];
-    if (b == ~0ull) continue;
-    const bool two = (uint32_t)(top[x] >> 32) - 1 != (uint32_t)(b >> 32);
+    const uint32_t c = threadIdx.x * PER + e;
+    cb[e] = sm.u.t.bot[c];
+    ct[e] = sm.u.t.top[c];
+    if (cb[e] == ~0ull) continue;
+    const int32_t x = x0 + (int32_t)c;
+    const bool two = (uint32_t)(ct[e] >> 32) - 1 != (uint32_t)(cb[e] >> 32);
     nlo += 1 + ((x == xmax && two) ? 1 : 0);
     nup += 1 + ((x == xmin && two) ? 1 : 0);
   }
-  uint32_t tlo, tup;
-  uint32_t olo = block_excl_scan(nlo, tlo);
-  uint32_t oup = block_excl_scan(nup, tup);
-  if (PASS == 0) {
-    if (threadIdx.x == 0) { cnt[2 * blockIdx.x] = tlo; cnt[2 * blockIdx.x + 1] = tup; }
-    return;
-  }
-  // Counts of the earlier chunks, summed by the whole workgroup.
-  uint32_t plo = 0, pup = 0;
-  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) {
-    plo += cnt[2 * b];
-    pup += cnt[2 * b + 1];
-  }
-  uint32_t blo, bup;
-  block_excl_scan(plo, blo);
-  block_excl_scan(pup, bup);
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    res->lcount = blo + tlo;
-    res->ucount = bup + tup;
-  }
-  olo += blo;
-  oup += bup;
+  uint32_t ul, uu;
+  uint32_t olo = block_excl_scan(nlo, ul);
+  uint32_t oup = block_excl_scan(nup, uu);  // (its barriers also end the table reads)
+#pragma unroll
   for (uint32_t e = 0; e < PER; ++e) {
-    const uint32_t x = x0 + e;
-    const uint64_t b = bot[x];
-    if (b == ~0ull) continue;
-    const uint64_t t = top[x];
-    const bool two = (uint32_t)(t >> 32) - 1 != (uint32_t)(b >> 32);
-    lst_lo[olo++] = bot_rec(x, b);
-    if (x == xmax && two) lst_lo[olo++] = top_rec(x, t);
-    if (x == xmin && two) lst_up[oup++] = bot_rec(x, b);
-    lst_up[oup++] = top_rec(x, t);
+    if (cb[e] == ~0ull) continue;
+    const uint32_t x = (uint32_t)(x0 + (int32_t)(threadIdx.x * PER + e));
+    const bool two = (uint32_t)(ct[e] >> 32) - 1 != (uint32_t)(cb[e] >> 32);
+    const Rec b = bot_rec(x, cb[e]), t = top_rec(x, ct[e]);
+    sm.u.l.lx[olo] = b.x; sm.u.l.ly[olo] = b.y; sm.u.l.li[olo] = b.i; ++olo;
+    if ((int32_t)x == xmax && two) { sm.u.l.lx[olo] = t.x; sm.u.l.ly[olo] = t.y; sm.u.l.li[olo] = t.i; ++olo; }
+    if ((int32_t)x == xmin && two) { sm.u.l.ux[oup] = b.x; sm.u.l.uy[oup] = b.y; sm.u.l.ui[oup] = b.i; ++oup; }
+    sm.u.l.ux[oup] = t.x; sm.u.l.uy[oup] = t.y; sm.u.l.ui[oup] = t.i; ++oup;
   }
+  __syncthreads();
+  uint32_t nl, nu;
+  dual_chain<kChunkMaxc>(sm.u.l.lx, sm.u.l.ly, sm.u.l.li, ul, sm.u.l.ux, sm.u.l.uy, sm.u.l.ui, uu,
+                         sm.cnt_l, sm.cnt_u, sm.wij_l, sm.wij_u, nl, nu);
+  Rec* dl = dst + (size_t)k * kChunkStride;
+  Rec* du = dst + cap + (size_t)k * kChunkStride;
+  for (uint32_t i = threadIdx.x; i < nl; i += kBlock) {
+    Rec r;
+    r.x = sm.u.l.lx[i]; r.y = sm.u.l.ly[i]; r.i = sm.u.l.li[i]; r.pad = 0;
+    dl[i] = r;
+  }
+  for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
+    Rec r;
+    r.x = sm.u.l.ux[i]; r.y = sm.u.l.uy[i]; r.i = sm.u.l.ui[i]; r.pad = 0;
+    du[i] = r;
+  }
+  if (threadIdx.x == 0) { wcnt[k] = nl; wcnt[kChunks + k] = nu; }
+}
+
+// Concatenate the chunk chains of both lists in chunk order (grid 2 x
+// kChunks): chain k moves to the sum of the chain lengths before it; the last
+// chunk records the packed length in pack[q].
+__global__ __launch_bounds__(kBlock) void k_lg_pack(const Rec* __restrict__ src,
+                                                    Rec* __restrict__ dst, size_t cap,
+                                                    const uint32_t* __restrict__ wcnt,
+                                                    uint32_t* __restrict__ pack) {
+  const uint32_t q = blockIdx.x / kChunks, k = blockIdx.x % kChunks;
+  const uint32_t* wc = wcnt + q * kChunks;
+  uint32_t part = 0;
+  for (uint32_t i = threadIdx.x; i < k; i += kBlock) part += wc[i];
+  uint32_t off;
+  block_excl_scan(part, off);
+  const uint32_t h = wc[k];
+  if (threadIdx.x == 0 && k == kChunks - 1) pack[q] = off + h;
+  const Rec* s = src + q * cap + (size_t)k * kChunkStride;
+  Rec* d = dst + q * cap;
+  for (uint32_t i = threadIdx.x; i < h; i += kBlock) d[off + i] = s[i];
 }
 
 constexpr int kWin = 4096;
@@ -1110,12 +1326,15 @@ __global__ __launch_bounds__(kBlock) void k_large_out(const Rec* __restrict__ lo
                                                       uint32_t host_n) {
   const uint32_t nl = res->fold_cnt[0], nu = res->fold_cnt[1], cin = res->cin;
   const uint32_t h = nl + (nu > 2 ? nu - 2 : 0);
-  for (uint32_t k = threadIdx.x; k < h; k += kBlock) {
+  // Every workgroup writes its share of the indices (the writes to host
+  // memory are latency-bound); workgroup 0 the result block. The host reads
+  // them after the kernel has completed.
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < h; k += gridDim.x * kBlock) {
     const uint32_t v = k < nl ? lo[k].i : up[nu - 2 - (k - nl)].i;
     res_idx[k] = v;
     if (host && k < host_n) host_idx[k] = v;
   }
-  __syncthreads();
+  if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
     res->h = h;
     res->status = RES_DONE;
@@ -1362,53 +1581,45 @@ hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* i
   return hipGetLastError();
 }
 
-hipError_t launch_col_build(const Rec* in, const uint32_t* in_count, uint32_t max_in,
-                            uint64_t* bot, uint64_t* top, uint32_t* cnt, Rec* lst_lo, Rec* lst_up,
-                            const Octagon* oct, Result* res, hipStream_t st, LaunchHook* hk) {
-  hooked(hk, "lg_col_init", [&] {
-    hipLaunchKernelGGL(k_col_init, dim3(1024), dim3(kBlock), 0, st, bot, top);
-  });
-  uint32_t g = (max_in + kBlock - 1) / kBlock;
-  if (g < 1) g = 1;
-  if (g > 4096) g = 4096;
-  hooked(hk, "lg_col_scatter", [&] {
-    hipLaunchKernelGGL(k_col_scatter, dim3(g), dim3(kBlock), 0, st, in, in_count, bot, top);
-  });
-  hooked(hk, "lg_col_emit", [&] {
-    hipLaunchKernelGGL(k_col_emit<0>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
-                       lst_up, oct, res);
-  });
-  hooked(hk, "lg_col_emit", [&] {
-    hipLaunchKernelGGL(k_col_emit<1>, dim3(kColBlocks), dim3(kBlock), 0, st, bot, top, cnt, lst_lo,
-                       lst_up, oct, res);
-  });
-  return hipGetLastError();
-}
-
 // The large-hull path from the records in[0..*in_count) (at most max_in)
-// to the hull in res_idx, with no host round trip: column table, the
-// x-sorted lower and upper lists, window chains, packing, one fold per list,
-// output. lstA / lstB hold two lists of kColumns + 2 records each (lower,
-// then upper); wcnt holds 2 * kWinPerList counts.
-hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in,
-                             uint64_t* bot, uint64_t* top, uint32_t* colcnt, Rec* lstA, Rec* lstB,
+// to the hull in res_idx, with no host round trip: partition by column
+// chunk into `part` (max_in records), chunk chains into lstB, packed into
+// lstA, one fold per list, output. lstA / lstB hold two lists of
+// kLargeListCap records each (lower, then upper); phist holds kChunks x
+// kPartMax counts, ptot kChunks totals, wcnt 2 x kChunks chain lengths.
+hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in, Rec* part,
+                             uint32_t* phist, uint32_t* ptot, Rec* lstA, Rec* lstB,
                              uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
                              Result* host, uint32_t* host_idx, uint32_t host_n, hipStream_t st,
                              LaunchHook* hk) {
-  const size_t cap = size_t(kColumns) + 2;
-  Rec* Alo = lstA;
-  Rec* Aup = lstA + cap;
-  hipError_t e =
-      launch_col_build(in, in_count, max_in, bot, top, colcnt, Alo, Aup, oct, res, st, hk);
-  if (e != hipSuccess) return e;
-  // lcount and ucount are adjacent: the two list lengths.
-  static_assert(offsetof(Result, ucount) == offsetof(Result, lcount) + 4, "list lengths");
-  e = launch_list_chains(2, lstA, lstB, cap, nullptr, &res->lcount, 1u, wcnt, res->pack_cnt,
-                         res->fold_cnt, st, hk);
-  if (e != hipSuccess) return e;
+  const size_t cap = kLargeListCap;
+  uint32_t G = (max_in + 2047) / 2048;
+  if (G < 1) G = 1;
+  if (G > kPartMax) G = kPartMax;
+  hooked(hk, "lg_count", [&] {
+    hipLaunchKernelGGL(k_lg_count, dim3(G), dim3(kBlock), 0, st, in, in_count, phist);
+  });
+  hooked(hk, "lg_scan", [&] {
+    hipLaunchKernelGGL(k_lg_scan, dim3(kChunks), dim3(kBlock), 0, st, phist, G, ptot);
+  });
+  hooked(hk, "lg_scatter", [&] {
+    hipLaunchKernelGGL(k_lg_scatter, dim3(G), dim3(kBlock), 0, st, in, in_count, phist, ptot, part);
+  });
+  hooked(hk, "lg_chunk", [&] {
+    hipLaunchKernelGGL(k_lg_chunk, dim3(kChunks), dim3(kBlock), 0, st, part, ptot, oct, lstB, cap,
+                       wcnt);
+  });
+  hooked(hk, "lg_pack", [&] {
+    hipLaunchKernelGGL(k_lg_pack, dim3(2 * kChunks), dim3(kBlock), 0, st, lstB, lstA, cap, wcnt,
+                       res->pack_cnt);
+  });
+  hooked(hk, "lg_fold", [&] {
+    hipLaunchKernelGGL(k_fold, dim3(2), dim3(kBlock), 0, st, lstA, cap, res->pack_cnt, 1u,
+                       res->fold_cnt);
+  });
   hooked(hk, "lg_out", [&] {
-    hipLaunchKernelGGL(k_large_out, dim3(1), dim3(kBlock), 0, st, Alo, Aup, res, res_idx, host,
-                       host_idx, host_n);
+    hipLaunchKernelGGL(k_large_out, dim3(16), dim3(kBlock), 0, st, lstA, lstA + cap, res, res_idx,
+                       host, host_idx, host_n);
   });
   return hipGetLastError();
 }

@@ -20,13 +20,23 @@ constexpr int kHullTile = 2048;        // items per tile hull (LDS resident)
 constexpr int kFinalTile = 4096;       // items the single-workgroup final hull takes
 constexpr int kHullGridMax = 1024;
 constexpr int kMaxRounds = 48;
-constexpr uint32_t kLargeDirect = 1u << 18;  // survivors above which ch_hull skips the tile rounds
+constexpr uint32_t kLargeDirect = 4096;  // survivors above which ch_hull skips the tile rounds
 constexpr uint32_t kHullCapMax = 1u << 21;  // strict vertices of a hull on the grid
 
 // Column table for large hulls: one bottom and one top entry per grid column.
 constexpr uint32_t kColumns = 1u << 20;
 constexpr uint32_t kColChunk = 4096;   // columns per compaction block
 constexpr uint32_t kColBlocks = kColumns / kColChunk;
+
+// Large-hull path of ch_hull: the records are partitioned by column chunk
+// (kChunkCols columns each, kChunks chunks) by kPartMax workgroups at most;
+// one workgroup per chunk keeps the bottom and top point of each of its
+// columns in LDS and chains them; the chunk chains are packed and folded.
+constexpr uint32_t kChunkCols = 2048;
+constexpr uint32_t kChunks = kColumns / kChunkCols;
+constexpr uint32_t kChunkStride = kChunkCols + 2;  // list slots per chunk (a chain holds <= kChunkCols + 1)
+constexpr uint32_t kPartMax = 512;
+constexpr size_t kLargeListCap = size_t(kChunks) * kChunkStride;  // records per list
 
 constexpr uint32_t kCountDomain = 0xFFFFFFFFu;
 
@@ -93,7 +103,7 @@ struct Result {
   uint32_t cin;        // input count of the latest hull round
   uint32_t ncand;      // candidate records of the fused pass (0 without one)
   uint32_t mode;       // how the fused pass ran (ch_hull_info.single_read)
-  uint32_t pad;
+  uint32_t cand_surv;  // 1: the octagon test was skipped, the survivors are the candidate records
   uint32_t round_cnt[kMaxRounds];   // records written by round r (index r+1 = output of round r)
   uint32_t round_tile[kMaxRounds];  // dynamic tile counter of round r
   uint32_t pack_cnt[2];             // large-hull path: window chains packed (lower, upper)
@@ -144,7 +154,7 @@ constexpr uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) 
 // Workspace layout. ch_filter uses the prefix up to `filter_end`.
 struct Layout {
   size_t hdr, res, res_idx, partials, part_bad, tstat, staging, filter_end;
-  size_t surv, recA, recB, colbot, coltop, colcnt, lstA, lstB, wcnt, poly, samp, total;
+  size_t surv, recA, recB, phist, ptot, lstA, lstB, wcnt, poly, samp, total;
 };
 
 constexpr Layout layout(uint32_t n) {
@@ -165,18 +175,18 @@ constexpr Layout layout(uint32_t n) {
   L.recA = o;      o = align_up(o + m * sizeof(Rec), 256);
   L.recB = o;      o = align_up(o + m * sizeof(Rec), 256);
   if (n <= (uint32_t)kFinalTile) {  // one workgroup: no rounds, no large-hull path
-    L.colbot = L.coltop = L.colcnt = L.lstA = L.lstB = L.wcnt = L.poly = L.samp = o;
+    L.phist = L.ptot = L.lstA = L.lstB = L.wcnt = L.poly = L.samp = o;
     L.total = o;
     return L;
   }
-  L.colbot = o;    o = align_up(o + size_t(kColumns) * 8, 256);
-  L.coltop = o;    o = align_up(o + size_t(kColumns) * 8, 256);
-  L.colcnt = o;    o = align_up(o + size_t(kColBlocks) * 2 * 4, 256);
-  // Lower / upper candidate chains: at most 2 per column (+1).
-  const size_t chain_cap = size_t(kColumns) + 2;
-  L.lstA = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
-  L.lstB = o;      o = align_up(o + 2 * chain_cap * sizeof(Rec), 256);
-  L.wcnt = o;      o = align_up(o + 2 * (chain_cap / kHullTile + 4) * 4, 256);
+  // Large-hull path: the partition's count table (chunk-major) and chunk
+  // totals, then the lower and upper lists (kLargeListCap records each) in
+  // two buffers, and the chain length of every chunk of both lists.
+  L.phist = o;     o = align_up(o + size_t(kChunks) * kPartMax * 4, 256);
+  L.ptot = o;      o = align_up(o + size_t(kChunks) * 4, 256);
+  L.lstA = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
+  L.lstB = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
+  L.wcnt = o;      o = align_up(o + 2 * size_t(kChunks) * 4, 256);
   // Refined filter: the sample polygon and the direction maxima.
   L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
   L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kLutBins) * 4 +

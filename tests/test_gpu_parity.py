@@ -217,6 +217,45 @@ def test_many_survivors_go_straight_to_large_path(ctx):
     assert info["large_path"] == 1 and info["rounds"] == 0, info
 
 
+@pytest.mark.parametrize("wait", ["poll", "stream"])
+@pytest.mark.parametrize("case", ["uniform", "ring", "polygon", "parabola"])
+def test_tile_round_path(case, wait):
+    """The hull path through the tile rounds (CH_LARGE_DIRECT above the
+    survivor count: tile hulls, then a block hull, or the large-hull path
+    when a round stops shrinking), with either wait for the block hull's
+    result (watching its status word or the stream), against the oracle."""
+    import os
+    import paper_2209_12310_amd as ch
+    _say(f"tile round path: {case}, wait {wait}")
+    if case == "uniform":
+        xy = workloads.uniform(10_000_000, 48)
+    elif case == "ring":
+        xy = workloads.annulus(300_000, 49)
+    elif case == "polygon":
+        xy = to_xy(convex_lattice_polygon(60))
+    else:
+        i = np.arange(20_000, dtype=np.int64)
+        xy = to_xy(np.stack([48 * i, (i * i) >> 9], 1))
+    old = {k: os.environ.get(k) for k in ("CH_LARGE_DIRECT", "CH_HULL_WAIT")}
+    os.environ["CH_LARGE_DIRECT"] = str(1 << 30)
+    os.environ["CH_HULL_WAIT"] = wait
+    try:
+        c = ch.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        _check_hull(c, xy)
+        info = c.last_hull_info()
+        if info["survivors"] > 4096:
+            assert info["rounds"] >= 1, info
+    finally:
+        c.close()
+
+
 def test_max_points(ctx):
     """CH_MAX_POINTS = 2^31 - 1 points (17 GB of input, ~112 GB of workspace):
     uniform interior points strictly inside the grid square, its four corners
