@@ -456,7 +456,7 @@ def _serve_views(pools, sizes, kinds, seeds):
 
 
 def bench_serve(ctx, duration_s: float = 60.0, arena_gb: int = 64, streams: int = 4,
-                plain_s: float = 15.0) -> dict:
+                plain_s: float = 15.0, max_batch_points: int = 0, rate=None) -> dict:
     """Serving: Poisson arrivals of host-resident requests (sizes log-uniform
     in [1e2, 1e7], kinds uniform / normal / wide annulus, seed 4) through the
     ch_serve server; latency = completion - scheduled arrival, including
@@ -477,7 +477,7 @@ def bench_serve(ctx, duration_s: float = 60.0, arena_gb: int = 64, streams: int 
     pools = {k: torch.from_numpy(workloads.by_kind(k, pool_n, 90 + i)).pin_memory()
              for i, k in enumerate(("uniform", "normal", "annulus_wide"))}
     arena = torch.empty(arena_gb << 30, dtype=torch.uint8, device="cuda:0")
-    srv = ctx.serve(arena, n_streams=streams)
+    srv = ctx.serve(arena, n_streams=streams, max_batch_points=max_batch_points)
     try:
         # Capacity on a saturated burst.
         _, bs, bk, bseed = workloads.serve_trace(1e9, 1e9, seed=5, max_requests=1500)
@@ -487,7 +487,8 @@ def bench_serve(ctx, duration_s: float = 60.0, arena_gb: int = 64, streams: int 
         tick = [srv.submit(v) for v in burst]
         last = max(int(srv.wait(t)[1][2]) for t in tick)
         capacity = len(burst) / ((last - t0) * 1e-9)
-        rate = 0.7 * capacity
+        if rate is None:
+            rate = 0.7 * capacity
         times, sizes, kinds, seeds = workloads.serve_trace(rate, duration_s, seed=4)
         views = _serve_views(pools, sizes, kinds, seeds)
         log(f"serve: {len(views)} requests at {rate:.0f}/s for {duration_s} s")
@@ -553,15 +554,18 @@ def bench_serve(ctx, duration_s: float = 60.0, arena_gb: int = 64, streams: int 
     pend = time.monotonic_ns()
     return {"workload": "serve_poisson", "requests": len(views), "rate_hz": round(rate, 1),
             "duration_s": duration_s, "streams": streams, "arena_gb": arena_gb,
+            "max_batch_points": max_batch_points,
             "mean_points": round(float(np.mean(sizes)), 1),
             "capacity_hulls_per_s": round(capacity, 1),
             "hulls_per_s": round(len(views) / ((done_max - start) * 1e-9), 1),
             "p50_us": round(pct(lat, 50), 1), "p99_us": round(pct(lat, 99), 1),
             "batches": st["batches"],
             "latency_breakdown": breakdown,
+            "h2d_gbs": round(len(views) / ((done_max - start) * 1e-9) * float(np.mean(sizes)) * 8 / 1e9, 2),
             "plain_requests": len(plat),
             "plain_hulls_per_s": round(len(plat) / ((pend - pstart) * 1e-9), 1),
-            "plain_p50_us": round(pct(plat, 50), 1), "plain_p99_us": round(pct(plat, 99), 1),
+            "plain_p50_us": round(pct(plat, 50), 1) if plat else None,
+            "plain_p99_us": round(pct(plat, 99), 1) if plat else None,
             "plain_trace_s": plain_s,
             "input": "pinned host memory, copied to the device inside the measured latency"}
 
@@ -595,6 +599,10 @@ def main() -> int:
     ap.add_argument("--batch-params", default=None,
                     help="JSON batch parameters to use instead of tuning (profiling runs)")
     ap.add_argument("--no-plain", action="store_true", help="skip batch plain mode (profiling runs)")
+    ap.add_argument("--only-serve", action="store_true", help="measure serving alone")
+    ap.add_argument("--serve-duration", type=float, default=60.0)
+    ap.add_argument("--serve-plain-s", type=float, default=15.0)
+    ap.add_argument("--serve-max-batch-points", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -611,6 +619,16 @@ def main() -> int:
         bp = json.loads(args.batch_params) if args.batch_params else None
         print(json.dumps({"batch": bench_batch(ctx, max(5, min(args.steps, 20)), args.warmup, bp,
                                                not args.no_plain)}), flush=True)
+        ctx.close()
+        return 0
+    if args.only_serve:
+        import torch
+
+        import paper_2209_12310_amd as ch
+        torch.zeros(1, device="cuda:0")  # torch's device runtime first, then the library's context
+        ctx = ch.Context(0)
+        print(json.dumps({"serve": bench_serve(ctx, args.serve_duration, plain_s=args.serve_plain_s,
+                                               max_batch_points=args.serve_max_batch_points)}), flush=True)
         ctx.close()
         return 0
     workload = args.workload
@@ -742,7 +760,9 @@ def main() -> int:
         out["batch"] = bench_batch(ctx, max(5, min(args.steps, 20)), 1)
         torch.cuda.synchronize()
     if not args.no_serve:
-        out["serve"] = bench_serve(ctx)
+        out["serve"] = bench_serve(ctx, args.serve_duration, plain_s=args.serve_plain_s,
+                                   max_batch_points=args.serve_max_batch_points)
+
     if not args.no_cpu:
         log("cpu baseline (oracle) and the paper's architecture")
         t = torch.from_numpy(xy).to(dev)

@@ -309,8 +309,9 @@ typedef struct {
   uint32_t max_inflight;     /* requests submitted and not yet collected by          */
                              /* ch_serve_wait; 0 means 65536                         */
   int n_streams;             /* worker streams and arena slots, 1..16; 0 means 4     */
-  uint64_t max_batch_points; /* points per batch at most; 0 means no cap beyond      */
-                             /* what a slot holds                                    */
+  uint64_t max_batch_points; /* points a batch of several requests holds at most    */
+                             /* (a larger request runs alone); 0 means no cap       */
+                             /* beyond what a slot holds                            */
 } ch_serve_config;
 
 typedef struct ch_server ch_server;

@@ -961,12 +961,21 @@ __global__ __launch_bounds__(kBlock) void k_lg_scan(uint32_t* __restrict__ hist,
 
 // First record of every chunk: exclusive scan of the chunk totals into s_base.
 __device__ __forceinline__ void chunk_bases(const uint32_t* __restrict__ tot, uint32_t* s_base) {
-  static_assert(kChunks == 2 * kBlock, "two chunks per thread");
-  const uint32_t t0 = tot[2 * threadIdx.x], t1 = tot[2 * threadIdx.x + 1];
+  constexpr uint32_t E = kChunks / kBlock;  // chunks per thread
+  static_assert(E * kBlock == kChunks, "whole chunks per thread");
+  uint32_t t[E], sum = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    t[e] = tot[E * threadIdx.x + e];
+    sum += t[e];
+  }
   uint32_t all;
-  const uint32_t e = block_excl_scan(t0 + t1, all);
-  s_base[2 * threadIdx.x] = e;
-  s_base[2 * threadIdx.x + 1] = e + t0;
+  uint32_t run = block_excl_scan(sum, all);
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    s_base[E * threadIdx.x + e] = run;
+    run += t[e];
+  }
   if (threadIdx.x == 0) s_base[kChunks] = all;
   __syncthreads();
 }
@@ -1106,22 +1115,24 @@ __global__ __launch_bounds__(kBlock) void k_lg_chunk(const Rec* __restrict__ par
   if (threadIdx.x == 0) { wcnt[k] = nl; wcnt[kChunks + k] = nu; }
 }
 
-// Concatenate the chunk chains of both lists in chunk order (grid 2 x
-// kChunks): chain k moves to the sum of the chain lengths before it; the last
-// chunk records the packed length in pack[q].
+// Concatenate the pieces of both lists in order (grid 2 x nper): piece k of
+// list q (cnt[q * nper + k] records at src + q * cap + k * stride) moves to
+// the sum of the piece lengths before it; the last piece records the
+// packed length in pack[q].
 __global__ __launch_bounds__(kBlock) void k_lg_pack(const Rec* __restrict__ src,
                                                     Rec* __restrict__ dst, size_t cap,
-                                                    const uint32_t* __restrict__ wcnt,
+                                                    size_t stride, uint32_t nper,
+                                                    const uint32_t* __restrict__ cnt,
                                                     uint32_t* __restrict__ pack) {
-  const uint32_t q = blockIdx.x / kChunks, k = blockIdx.x % kChunks;
-  const uint32_t* wc = wcnt + q * kChunks;
+  const uint32_t q = blockIdx.x / nper, k = blockIdx.x % nper;
+  const uint32_t* wc = cnt + q * nper;
   uint32_t part = 0;
   for (uint32_t i = threadIdx.x; i < k; i += kBlock) part += wc[i];
   uint32_t off;
   block_excl_scan(part, off);
   const uint32_t h = wc[k];
-  if (threadIdx.x == 0 && k == kChunks - 1) pack[q] = off + h;
-  const Rec* s = src + q * cap + (size_t)k * kChunkStride;
+  if (threadIdx.x == 0 && k == nper - 1) pack[q] = off + h;
+  const Rec* s = src + q * cap + (size_t)k * stride;
   Rec* d = dst + q * cap;
   for (uint32_t i = threadIdx.x; i < h; i += kBlock) d[off + i] = s[i];
 }
@@ -1292,6 +1303,63 @@ __global__ __launch_bounds__(kBlock) void k_fold(Rec* __restrict__ lists, size_t
   const uint32_t r = ((lower_mask >> q) & 1u) ? fold_chain<true>(sm, l, m, l)
                                                : fold_chain<false>(sm, l, m, l);
   if (threadIdx.x == 0) fold[q] = r;
+}
+
+// Groups of kGroupChunks consecutive chunk chains of both lists (grid 2 x
+// kGroups): up to kWin records are chained together in LDS (the chain of
+// x-ordered pieces is the chain of all their points, and each piece already
+// holds every vertex of its own range), so the fold sees few records; a
+// larger group is passed on unchanged. Group g of list q goes to
+// dst + q * cap + g * kGroupStride, its length to gcnt[q * kGroups + g].
+__global__ __launch_bounds__(kBlock) void k_lg_group(const Rec* __restrict__ src,
+                                                     Rec* __restrict__ dst, size_t cap,
+                                                     const uint32_t* __restrict__ wcnt,
+                                                     uint32_t* __restrict__ gcnt) {
+  __shared__ WinSmem<kWin> sm;
+  __shared__ uint32_t s_off[kGroupChunks + 1];
+  const uint32_t q = blockIdx.x / kGroups, g = blockIdx.x % kGroups;
+  const uint32_t* wl = wcnt + q * kChunks;
+  const uint32_t* wc = wl + g * kGroupChunks;
+  if (threadIdx.x == 0) {
+    uint32_t o = 0;
+    for (uint32_t j = 0; j < kGroupChunks; ++j) {
+      s_off[j] = o;
+      o += wc[j];
+    }
+    s_off[kGroupChunks] = o;
+  }
+  // The whole list's length: a list the fold takes in one batch anyway is
+  // passed on unchanged.
+  uint32_t part = 0;
+  for (uint32_t k = threadIdx.x; k < kChunks; k += kBlock) part += wl[k];
+  uint32_t list_len;
+  block_excl_scan(part, list_len);  // (its barriers also publish s_off)
+  const uint32_t total = s_off[kGroupChunks];
+  const Rec* sg = src + q * cap + (size_t)(g * kGroupChunks) * kChunkStride;
+  Rec* d = dst + q * cap + (size_t)g * kGroupStride;
+  if (total > (uint32_t)kWin || list_len <= (uint32_t)kWin) {
+    for (uint32_t j = 0; j < kGroupChunks; ++j) {
+      const uint32_t c = s_off[j + 1] - s_off[j];
+      for (uint32_t i = threadIdx.x; i < c; i += kBlock) d[s_off[j] + i] = sg[(size_t)j * kChunkStride + i];
+    }
+    if (threadIdx.x == 0) gcnt[q * kGroups + g] = total;
+    return;
+  }
+  for (uint32_t j = 0; j < kGroupChunks; ++j) {
+    const uint32_t c = s_off[j + 1] - s_off[j];
+    for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
+      const Rec r = sg[(size_t)j * kChunkStride + i];
+      sm.px[s_off[j] + i] = r.x; sm.py[s_off[j] + i] = r.y; sm.pi[s_off[j] + i] = r.i;
+    }
+  }
+  __syncthreads();
+  const uint32_t h = q == 0 ? window_chain<true>(sm, total) : window_chain<false>(sm, total);
+  for (uint32_t i = threadIdx.x; i < h; i += kBlock) {
+    Rec r;
+    r.x = sm.px[i]; r.y = sm.py[i]; r.i = sm.pi[i]; r.pad = 0;
+    d[i] = r;
+  }
+  if (threadIdx.x == 0) gcnt[q * kGroups + g] = h;
 }
 
 // Window chains, packing and one fold per list, for NL lists as k_window
@@ -1583,10 +1651,11 @@ hipError_t launch_hull_round(uint32_t grid, const Rec* in_rec, const uint32_t* i
 
 // The large-hull path from the records in[0..*in_count) (at most max_in)
 // to the hull in res_idx, with no host round trip: partition by column
-// chunk into `part` (max_in records), chunk chains into lstB, packed into
-// lstA, one fold per list, output. lstA / lstB hold two lists of
-// kLargeListCap records each (lower, then upper); phist holds kChunks x
-// kPartMax counts, ptot kChunks totals, wcnt 2 x kChunks chain lengths.
+// chunk into `part` (max_in records), chunk chains into lstB, groups of them
+// chained into lstA, packed into lstB, one fold per list, output. lstA /
+// lstB hold two lists of kLargeListCap records each (lower, then upper);
+// phist holds kChunks x kPartMax counts, ptot kChunks totals, wcnt
+// 2 x (kChunks + kGroups) chain lengths.
 hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t max_in, Rec* part,
                              uint32_t* phist, uint32_t* ptot, Rec* lstA, Rec* lstB,
                              uint32_t* wcnt, const Octagon* oct, Result* res, uint32_t* res_idx,
@@ -1609,16 +1678,21 @@ hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t m
     hipLaunchKernelGGL(k_lg_chunk, dim3(kChunks), dim3(kBlock), 0, st, part, ptot, oct, lstB, cap,
                        wcnt);
   });
+  uint32_t* gcnt = wcnt + 2 * kChunks;
+  hooked(hk, "lg_group", [&] {
+    hipLaunchKernelGGL(k_lg_group, dim3(2 * kGroups), dim3(kBlock), 0, st, lstB, lstA, cap, wcnt,
+                       gcnt);
+  });
   hooked(hk, "lg_pack", [&] {
-    hipLaunchKernelGGL(k_lg_pack, dim3(2 * kChunks), dim3(kBlock), 0, st, lstB, lstA, cap, wcnt,
-                       res->pack_cnt);
+    hipLaunchKernelGGL(k_lg_pack, dim3(2 * kGroups), dim3(kBlock), 0, st, lstA, lstB, cap,
+                       kGroupStride, kGroups, gcnt, res->pack_cnt);
   });
   hooked(hk, "lg_fold", [&] {
-    hipLaunchKernelGGL(k_fold, dim3(2), dim3(kBlock), 0, st, lstA, cap, res->pack_cnt, 1u,
+    hipLaunchKernelGGL(k_fold, dim3(2), dim3(kBlock), 0, st, lstB, cap, res->pack_cnt, 1u,
                        res->fold_cnt);
   });
   hooked(hk, "lg_out", [&] {
-    hipLaunchKernelGGL(k_large_out, dim3(16), dim3(kBlock), 0, st, lstA, lstA + cap, res, res_idx,
+    hipLaunchKernelGGL(k_large_out, dim3(16), dim3(kBlock), 0, st, lstB, lstB + cap, res, res_idx,
                        host, host_idx, host_n);
   });
   return hipGetLastError();

@@ -32,11 +32,14 @@ constexpr uint32_t kColBlocks = kColumns / kColChunk;
 // (kChunkCols columns each, kChunks chunks) by kPartMax workgroups at most;
 // one workgroup per chunk keeps the bottom and top point of each of its
 // columns in LDS and chains them; the chunk chains are packed and folded.
-constexpr uint32_t kChunkCols = 2048;
+constexpr uint32_t kChunkCols = 1024;
 constexpr uint32_t kChunks = kColumns / kChunkCols;
 constexpr uint32_t kChunkStride = kChunkCols + 2;  // list slots per chunk (a chain holds <= kChunkCols + 1)
 constexpr uint32_t kPartMax = 512;
 constexpr size_t kLargeListCap = size_t(kChunks) * kChunkStride;  // records per list
+constexpr uint32_t kGroupChunks = 32;                  // chunk chains chained together
+constexpr uint32_t kGroups = kChunks / kGroupChunks;
+constexpr size_t kGroupStride = size_t(kGroupChunks) * kChunkStride;
 
 constexpr uint32_t kCountDomain = 0xFFFFFFFFu;
 
@@ -186,7 +189,7 @@ constexpr Layout layout(uint32_t n) {
   L.ptot = o;      o = align_up(o + size_t(kChunks) * 4, 256);
   L.lstA = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
   L.lstB = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
-  L.wcnt = o;      o = align_up(o + 2 * size_t(kChunks) * 4, 256);
+  L.wcnt = o;      o = align_up(o + 2 * size_t(kChunks + kGroups) * 4, 256);
   // Refined filter: the sample polygon and the direction maxima.
   L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
   L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kLutBins) * 4 +

@@ -242,9 +242,9 @@ uint64_t ch_serve_max_request_points(const ch_serve_config* cfg) {
   if (!cfg) return 0;
   const size_t slot = slot_bytes_of(cfg);
   if (!slot) return 0;
-  uint64_t m = max_points_for_slot(slot);
-  if (cfg->max_batch_points && m > cfg->max_batch_points) m = cfg->max_batch_points;
-  return m;
+  // max_batch_points caps what several requests share; one request above it
+  // still runs alone, so only the slot bounds a request.
+  return max_points_for_slot(slot);
 }
 
 ch_status ch_serve_start(ch_ctx* ctx, const ch_serve_config* cfg, ch_server** out) {
