@@ -643,6 +643,11 @@ struct StageCap<Rec> {
 // one wave sync when they fit.
 constexpr int kQueue = 128;
 constexpr int kQueueF = 256;
+// Candidate records the fused pass stages per wave before one reservation
+// in the shared list (a device-scope atomic on one counter, whose round
+// trips serialise: many candidates want few, large flushes). Sized so that
+// two workgroups still fit a CU's LDS with the polygon, wedge table and queue.
+constexpr int kCapF = 832;
 
 // The candidates' octagon test is skipped when it removes fewer than 1 in
 // kSkipRatio of the first kSkipEst candidate records.
@@ -1123,7 +1128,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hull(const float* __restrict__ 
                                                       SampleDirs* __restrict__ sd,
                                                       Rec* __restrict__ cand,
                                                       uint32_t narrow_blocks) {
-  constexpr int kCapW = StageCap<Rec>::value;
+  constexpr int kCapW = kCapF;
   __shared__ Rec s_buf[kWaves][kCapW];
   __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ uint32_t s_lut[kLutBins];
