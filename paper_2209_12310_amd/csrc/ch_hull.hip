@@ -404,12 +404,22 @@ __device__ __forceinline__ void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
 template <int T>
 __device__ bool small_chains(HullSmem<T>& sm, uint32_t kept, uint32_t& nl, uint32_t& nu) {
   static_assert(kWaves == 4, "two waves per chain");
+  static_assert(T >= 4 * kSmallChain, "scratch laid over px / py");
+  static_assert(sizeof(sm.cnt) + sizeof(sm.cnt2) + sizeof(sm.wij) + sizeof(sm.wij2) >=
+                    2 * kSmallChain * sizeof(uint64_t),
+                "chain vertices laid over the merge scratch");
   __shared__ uint32_t s_n[2], s_vc[2][2];
-  __shared__ int32_t s_x[2][kSmallChain], s_y[2][kSmallChain];
-  __shared__ uint32_t s_ui[2][kSmallChain];
-  __shared__ uint64_t s_vt[2][kSmallChain];  // chain vertices (x<<20 | y)
-  __shared__ double s_pl[2][64], s_pr[2][64];  // second half's bounds (chains of <= 64)
-  __shared__ uint32_t s_pf[2][64];
+  // Scratch laid over storage that is dead while this runs (fewer bytes of
+  // LDS per workgroup, so more workgroups per CU): px / py (written only by
+  // the final placement, after every read of the scratch) and the chain
+  // builders' merge tables (unused on this path).
+  int32_t (*s_x)[kSmallChain] = reinterpret_cast<int32_t (*)[kSmallChain]>(sm.px);
+  int32_t (*s_y)[kSmallChain] = reinterpret_cast<int32_t (*)[kSmallChain]>(sm.px + 2 * kSmallChain);
+  uint32_t (*s_ui)[kSmallChain] = reinterpret_cast<uint32_t (*)[kSmallChain]>(sm.px + 4 * kSmallChain);
+  double (*s_pl)[64] = reinterpret_cast<double (*)[64]>(sm.py);
+  double (*s_pr)[64] = reinterpret_cast<double (*)[64]>(sm.py + 256);
+  uint32_t (*s_pf)[64] = reinterpret_cast<uint32_t (*)[64]>(sm.py + 512);
+  uint64_t (*s_vt)[kSmallChain] = reinterpret_cast<uint64_t (*)[kSmallChain]>(sm.cnt);  // chain vertices (x<<20 | y)
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -564,9 +574,15 @@ __device__ __forceinline__ constexpr int dir_y(int d) {
 template <int T>
 __device__ uint32_t tile_hull_core(HullSmem<T>& sm, uint32_t cnt, uint32_t& nl, uint32_t& nu) {
   constexpr uint32_t E = T / kBlock;  // items per thread: i = threadIdx.x + e * kBlock
-  __shared__ uint64_t s_ext[kWaves][16];
-  __shared__ int32_t s_vx[16], s_vy[16];
-  __shared__ double s_ex[16], s_ney[16], s_c[16];
+  // The pre-filter's scratch lies over the sort keys, written only after
+  // its last read (the keys follow the compaction scan's barriers).
+  static_assert(T >= 256, "pre-filter scratch laid over the keys");
+  uint64_t (*s_ext)[16] = reinterpret_cast<uint64_t (*)[16]>(sm.a.key);
+  int32_t* s_vx = reinterpret_cast<int32_t*>(sm.a.key + 64);
+  int32_t* s_vy = reinterpret_cast<int32_t*>(sm.a.key + 72);
+  double* s_ex = reinterpret_cast<double*>(sm.a.key + 80);
+  double* s_ney = reinterpret_cast<double*>(sm.a.key + 96);
+  double* s_c = reinterpret_cast<double*>(sm.a.key + 112);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // Extreme position per direction: max of (dot, -position) per thread, then
   // per wave (transposed DPP exchange: lane l ends with direction l mod 16),
@@ -846,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_hull_final(const Rec* __restrict__ i
 
 // Many workgroups: tiles of kHullTile candidates to tile hulls, appended to
 // out_rec (order between tiles is immaterial: the next round sorts again).
-__global__ __launch_bounds__(kBlock) void k_hull_round(const Rec* __restrict__ in_rec,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_hull_round(const Rec* __restrict__ in_rec,
                                                        const uint32_t* __restrict__ in_count,
                                                        Rec* __restrict__ out_rec,
                                                        uint32_t* __restrict__ out_count,
@@ -1522,7 +1538,7 @@ __device__ uint32_t big_set_hull(BigSmem& sm, Rec* X, Rec* Y, uint32_t c, int32_
 // that waits for the next tile-hull round (or, after the last one, for
 // k_batch_large). Workgroups take sets with a fixed stride.
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_batch_final(const uint64_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_final(const uint64_t* __restrict__ off,
                                                         uint32_t nsets,
                                                         const BatchHdr* __restrict__ bh,
                                                         SetState* __restrict__ sets, int stage,
@@ -1583,7 +1599,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_round_plan(const uint64_t* __r
 }
 
 // Tile hulls of one round, appended to the set's slice of the next buffer.
-__global__ __launch_bounds__(kBlock) void k_batch_round(const uint64_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_round(const uint64_t* __restrict__ off,
                                                         const BatchHdr* __restrict__ bh, int stage,
                                                         const SetTile* __restrict__ rtiles,
                                                         SetState* __restrict__ sets,
