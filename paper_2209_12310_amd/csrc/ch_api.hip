@@ -357,8 +357,8 @@ ch_status check_points(ch_ctx* ctx, const float* d_xy, uint32_t n) {
 ch_batch_params default_batch_params(int cu) {
   ch_batch_params p;
   p.tile_points = kBatchTile;
-  p.pass_blocks = (uint32_t)cu * 4;
-  p.hull_blocks = (uint32_t)cu * 3;
+  p.pass_blocks = (uint32_t)cu * 8;
+  p.hull_blocks = (uint32_t)cu * 9;  // three tile-hull workgroups per CU, three waves of them
   p.sample_min = kBatchSampleMin;
   return p;
 }
@@ -1022,11 +1022,11 @@ ch_status ch_tune_batch(ch_ctx* ctx, const float* d_xy, const uint64_t* d_off, u
   float best_ms = 0.f;
   ch_status st_all = time_of(best, best_ms);
   const uint32_t tiles[] = {4096, 8192, 16384, 32768};
-  const uint32_t passm[] = {2, 4, 8};
-  const uint32_t hullm[] = {2, 3, 4, 6};
+  const uint32_t passm[] = {2, 4, 8, 16};
+  const uint32_t hullm[] = {3, 6, 9, 12};
   const uint32_t smins[] = {1u << 13, 1u << 15, 1u << 17, 0xFFFFFFFFu};
   for (int dim = 0; dim < 4 && st_all == CH_OK; ++dim) {
-    const int nv = dim == 1 ? 3 : 4;
+    const int nv = 4;
     for (int i = 0; i < nv && st_all == CH_OK; ++i) {
       ch_batch_params c = best;
       if (dim == 0) c.tile_points = tiles[i];

@@ -648,6 +648,9 @@ constexpr int kQueueF = 256;
 // trips serialise: many candidates want few, large flushes). Sized so that
 // two workgroups still fit a CU's LDS with the polygon, wedge table and queue.
 constexpr int kCapF = 832;
+// Candidate records the batch pass stages per wave (its grid runs eight
+// workgroups per CU, so its LDS stays small).
+constexpr int kCapB = 128;
 
 // The candidates' octagon test is skipped when it removes fewer than 1 in
 // kSkipRatio of the first kSkipEst candidate records.
@@ -1514,6 +1517,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
   __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
+  __shared__ Rec s_cb[kWaves][kCapB];  // staged candidate records of the wave
   const uint32_t ntiles = bh->ntiles;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -1545,15 +1549,23 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
     keys_init(k);
     bool bad = false;
     float frac = 0.f;  // largest fractional part of a scaled coordinate (inner points)
-    uint32_t qn = 0;
-    // Candidates of the wave's ballot, appended with one atomic.
+    uint32_t qn = 0, cw = 0;
+    // Staged candidates go to the set's slice with one reservation per
+    // flush (a full buffer, or the end of the tile).
+    auto flush = [&]() {
+      uint32_t p = 0;
+      if (lane == 0) p = atomicAdd(&ss.ncand, cw);
+      p = __shfl(p, 0);
+      for (uint32_t i = lane; i < cw; i += 64) cand[base + p + i] = s_cb[w][i];
+      wave_sync();
+      cw = 0;
+    };
     auto emit = [&](bool keep, float x, float y, uint32_t gl) {
       const uint64_t bk = __ballot(keep);
       if (!bk) return;
-      uint32_t p = 0;
-      if (lane == 0) p = atomicAdd(&ss.ncand, popc64(bk));
-      p = __shfl(p, 0) + popc64(bk & lt);
-      if (keep) cand[base + p] = make_payload<Rec>(gl, x, y);
+      if (cw + popc64(bk) > (uint32_t)kCapB) flush();
+      if (keep) s_cb[w][cw + popc64(bk & lt)] = make_payload<Rec>(gl, x, y);
+      cw += popc64(bk);
     };
     // Queued points (outside the inner region): keys, then the exact test.
     auto drain = [&](uint32_t qb, uint32_t cnt) {
@@ -1635,6 +1647,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
       for (int u = 0; u < kU; ++u) v[u] = nx[u];
     }
     if (qn) drain(0, qn);
+    if (cw) flush();
     bad |= frac != 0.f;
     if (threadIdx.x == 0) {
       const uint32_t last = a2 + 2 * npairs;
