@@ -387,24 +387,36 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
   if (threadIdx.x == 0) out->nv = use ? m : 0u;
 }
 
-// Largest and smallest dot product over the sample points sp[0..cnt) (LDS)
-// in direction (a, b), with the positions of their first occurrences: the
-// maxima in the direction and in its opposite (whose dot product is the
-// negation). Every lane reads the same point (an LDS broadcast); the dot
-// products use 24-bit multiplies (|a|, |b| <= 1024, coordinates < 2^20).
+// Largest and smallest dot product over the sample points sp[0..cnt) (LDS,
+// cnt <= 2048) in direction (a, b), with the positions of the points that
+// attain them: the maxima in the direction and in its opposite (whose dot
+// product is the negation). Every lane reads the same point (an LDS
+// broadcast); the dot products use 24-bit multiplies (|a|, |b| <= 1024,
+// coordinates < 2^20, |dot| < 1.5 * 2^30). The scan keeps one int32 key per
+// side, the dot product with its low 11 bits replaced by the position, so a
+// max and a min carry the position along: the chosen point is extreme to
+// within 2^11 of its dot product (a vertex of the polygon only has to be an
+// input point), and the returned dot products are the exact ones of the
+// chosen points.
+static_assert(kBatchSample <= 2048 && kSamplePer <= 2048, "positions fit 11 bits");
 __device__ __forceinline__ void dir_minmax(const int2* __restrict__ sp, uint32_t cnt, int32_t a,
                                            int32_t b, int32_t& dmax, uint32_t& qmax,
                                            int32_t& dmin, uint32_t& qmin) {
-  dmax = INT32_MIN;
-  dmin = INT32_MAX;
-  qmax = qmin = 0;
+  int32_t kmax = INT32_MIN, kmin = INT32_MAX;
 #pragma unroll 8
   for (uint32_t q = 0; q < cnt; ++q) {
     const int2 p = sp[q];
     const int32_t e = __mul24(a, p.x) + __mul24(b, p.y);
-    if (e > dmax) { dmax = e; qmax = q; }
-    if (e < dmin) { dmin = e; qmin = q; }
+    const int32_t k = (e & ~0x7FF) | (int32_t)q;
+    kmax = k > kmax ? k : kmax;
+    kmin = k < kmin ? k : kmin;
   }
+  qmax = (uint32_t)kmax & 0x7FFu;
+  qmin = (uint32_t)kmin & 0x7FFu;
+  if (cnt == 0) qmax = qmin = 0;
+  const int2 pM = sp[qmax < cnt ? qmax : 0], pm = sp[qmin < cnt ? qmin : 0];
+  dmax = cnt ? __mul24(a, pM.x) + __mul24(b, pM.y) : INT32_MIN;
+  dmin = cnt ? __mul24(a, pm.x) + __mul24(b, pm.y) : INT32_MAX;
 }
 
 // Single set, before the fused pass. k_sample_dirs: workgroup b takes sample
