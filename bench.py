@@ -68,7 +68,7 @@ def kernel_alg_bytes(name: str, n: int, info: dict):
     return model.get(name)
 
 
-def kernel_roofline(stats: dict, n: int, info: dict, read_gbs=None) -> dict:
+def kernel_roofline(stats: dict, n: int, info: dict, read_gbs=None, workload=None) -> dict:
     """Roofline of the dominant kernel among those with a byte model, from
     the library's per-kernel HIP events; also names the kernel that takes the
     most time overall."""
@@ -84,16 +84,20 @@ def kernel_roofline(stats: dict, n: int, info: dict, read_gbs=None) -> dict:
     achieved = alg / (means[dom] * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg,
-         "mean_us": round(means[dom] * 1e3, 2), "dominant_overall": overall}
+         "mean_us": round(means[dom] * 1e3, 2), "dominant_overall": overall,
+        "traffic": load_traffic(workload, n, dom) if workload else None}
     if read_gbs:
         r["frac_of_read_stream"] = round(achieved / read_gbs, 4)
     return r
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_normal_1e8.json")
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
 KERNEL_SOURCES = ["paper_2209_12310_amd/csrc/ch_filter.hip", "paper_2209_12310_amd/csrc/ch_internal.hpp",
                   "paper_2209_12310_amd/csrc/ch_device.hpp", "paper_2209_12310_amd/csrc/ch_refine.hpp",
-                  "paper_2209_12310_amd/csrc/ch_refine.hip"]
+                  "paper_2209_12310_amd/csrc/ch_refine.hip", "paper_2209_12310_amd/csrc/ch_hull.hip"]
 
 
 def log(msg: str) -> None:
@@ -108,11 +112,12 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(n: int, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is absent or the kernel source changed since."""
+def load_traffic(workload: str, n: int, kernel: str):
+    """HBM bytes per launch of one kernel from the committed rocprofv3 counter
+    summary of this workload, or None when it is absent or the kernel source
+    changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -319,7 +324,7 @@ def bench_single(ctx, name: str, steps: int, warmup: int, read_gbs=None) -> dict
             "octagon_survivors": survivors, "hull_info": info, "h": int(hull.size),
             "kernels_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in stats.items() if v[0]},
             "kernel_launches_per_step": {k: round(v[0] / steps, 2) for k, v in stats.items() if v[0]},
-            "roofline": kernel_roofline(stats, n, info, read_gbs)}
+            "roofline": kernel_roofline(stats, n, info, read_gbs, name)}
 
 
 def pct(vals, q):
@@ -414,7 +419,8 @@ def bench_batch(ctx, steps: int, warmup: int, params=None, plain_mode: bool = Tr
         roof = {"bound": "hbm", "kernel": "batch_pass", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": 8 * n,
                 "mean_us": round(pass_ms * 1e3, 2),
-                "note": "8 B per point read; candidate records written are left out (lower bound)"}
+                "note": "8 B per point read; candidate records written are left out (lower bound)",
+                "traffic": load_traffic("batch_4096", n, "batch_pass")}
     # Plain mode: one synchronous ch_hull per set.
     plain = float("nan")
     if plain_mode:
@@ -696,7 +702,7 @@ def main() -> int:
     else:
         alg_bytes = 8 * n
     achieved = alg_bytes / mean_s / 1e9
-    traffic = load_traffic(n, dom)
+    traffic = load_traffic(workload, n, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
@@ -748,7 +754,8 @@ def main() -> int:
                                      "hbm_frac": out["hbm_frac_end_to_end"],
                                      "octagon_survivors": survivors, "hull_info": info,
                                      "h": int(hull.size), "kernels_us": {k: v["mean_us"] for k, v in kernels.items()},
-                                     "roofline": kernel_roofline(stats, n, info, read_stream["gbs"])}}
+                                     "roofline": kernel_roofline(stats, n, info, read_stream["gbs"],
+                                                                 workload)}}
     if not args.no_extra:
         for name in ("uniform_1e8", "annulus_1e8", "uniform_1e6"):
             if name == workload:

@@ -1436,49 +1436,101 @@ __device__ __forceinline__ double dec_f64(uint64_t e) {
   return __longlong_as_double((long long)b);
 }
 
-// One workgroup: tile lists and per-set state. Thread t owns a contiguous
-// group of sets; one exclusive scan gives every group its first tile.
+// Tile lists, per-set state and the sampler's list. Workgroup b owns sets
+// b kBlock .. b kBlock + kBlock - 1, one per thread. Every workgroup first
+// reads all offsets (a few KB, from L2) for the batch-wide facts: whether
+// they are valid (else every set is empty), the pass tiles of the sets before
+// its own and in all, and the sampled sets (batch_chunks > 0) per chunk count,
+// before its own and in all. It then writes its sets' pass tiles in set
+// order, resets their SetState, clears the polygon of each set without a
+// sample, and enters its sampled sets in the sampler's list, ordered by chunk
+// count from 4 down to 1 and by set within a count, so that the longest
+// sampler jobs are taken first.
 __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restrict__ off,
                                                        uint32_t nsets, uint64_t total_points,
-                                                       uint32_t tile,
+                                                       uint32_t tile, uint32_t sample_min,
                                                        BatchHdr* __restrict__ bh,
                                                        SetState* __restrict__ sets,
-                                                       SetTile* __restrict__ tiles) {
+                                                       SetTile* __restrict__ tiles,
+                                                       SamplePoly* __restrict__ polys,
+                                                       uint32_t* __restrict__ slist) {
+  static_assert(kBatchChunksMax == 4, "one list bucket per chunk count 4, 3, 2, 1");
+  constexpr int kVals = 10;  // tiles before, tiles in all, 4 buckets before, 4 in all
   __shared__ uint32_t s_bad;
+  __shared__ uint32_t s_red[kWaves][kVals];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t first = blockIdx.x * kBlock;
   if (threadIdx.x == 0) s_bad = (off[0] != 0 || off[nsets] != total_points) ? 1u : 0u;
   __syncthreads();
-  const uint32_t per = (nsets + kBlock - 1) / kBlock;
-  const uint32_t s0 = threadIdx.x * per;
-  const uint32_t s1 = s0 + per < nsets ? s0 + per : nsets;
-  for (uint32_t s = s0; s < s1; ++s)
+  for (uint32_t s = threadIdx.x; s < nsets; s += kBlock)
     if (off[s + 1] < off[s]) s_bad = 1u;
   __syncthreads();
   const bool bad = s_bad != 0;
-  uint32_t mine = 0;
-  for (uint32_t s = s0; s < s1 && !bad; ++s) {
-    const uint64_t n = off[s + 1] - off[s];
-    mine += (uint32_t)((n + tile - 1) / tile);
-  }
-  uint32_t total;
-  uint32_t t = block_excl_scan(mine, total);
-  for (uint32_t s = s0; s < s1; ++s) {
-    const uint32_t a = (uint32_t)off[s], b = bad ? a : (uint32_t)off[s + 1];
-    for (uint32_t p = a; p < b; p += tile) {
-      SetTile st;
-      st.set = s; st.begin = p; st.end = b - p > tile ? p + tile : b; st.pad = 0;
-      tiles[t++] = st;
+  // Sizes below 2^32 (the batch total is), so 32-bit divisions.
+  uint32_t v[kVals] = {};
+  for (uint32_t s = threadIdx.x; s < nsets && !bad; s += kBlock) {
+    const uint32_t n = (uint32_t)(off[s + 1] - off[s]);
+    const uint32_t t = n / tile + (n % tile ? 1u : 0u), c = batch_chunks(n, sample_min);
+    v[1] += t;
+    if (s < first) v[0] += t;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint32_t hit = c == 4 - k ? 1u : 0u;  // bucket k: chunk count 4 - k
+      v[6 + k] += hit;
+      v[2 + k] += s < first ? hit : 0u;
     }
+  }
+#pragma unroll
+  for (int k = 0; k < kVals; ++k) {
+    const uint32_t r = wave_allreduce(v[k], [](uint32_t a, uint32_t b) { return a + b; });
+    if (lane == 0) s_red[w][k] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kVals; ++k) {
+    v[k] = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v[k] += s_red[q][k];
+  }
+  const uint32_t s = first + threadIdx.x;
+  const bool own = s < nsets;
+  const uint32_t a = own ? (uint32_t)off[s] : 0u;
+  const uint32_t b = own && !bad ? (uint32_t)off[s + 1] : a;
+  const uint32_t c = own && !bad ? batch_chunks(b - a, sample_min) : 0u;
+  uint32_t unused;
+  uint32_t t = v[0] + block_excl_scan((b - a) / tile + ((b - a) % tile ? 1u : 0u), unused);
+  for (uint32_t p = a; p < b; p += tile) {
+    SetTile st;
+    st.set = s; st.begin = p; st.end = b - p > tile ? p + tile : b; st.pad = 0;
+    tiles[t++] = st;
+  }
+  if (own) {
     SetState& ss = sets[s];
     for (int k = 0; k < 8; ++k) ss.key[k] = 0ull;
     ss.bad = 0;
     ss.done = 0;
     ss.ncand = 0;
     for (int r = 0; r <= kBatchRounds; ++r) ss.cnt[r] = 0;
+    if (!c) polys[s].nv = 0;
   }
-  if (threadIdx.x == 0) {
-    bh->ntiles = total;
+  // Rank among this workgroup's sets of the same chunk count: two scans of
+  // two 16-bit counters each (at most kBlock per bucket).
+  const uint32_t k = 4 - c;  // bucket (4 = none)
+  const uint32_t e01 = block_excl_scan(c && k < 2 ? 1u << (16 * k) : 0u, unused);
+  const uint32_t e23 = block_excl_scan(c && k >= 2 ? 1u << (16 * (k - 2)) : 0u, unused);
+  if (c) {
+    const uint32_t rank = ((k < 2 ? e01 : e23) >> (16 * (k & 1))) & 0xFFFFu;
+    uint32_t start = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) start += j < k ? v[6 + j] : (j == k ? v[2 + j] : 0u);
+    slist[start + rank] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bh->ntiles = v[1];
     bh->bad_offsets = bad ? 1u : 0u;
     for (int r = 0; r <= kBatchRounds; ++r) bh->nround[r] = 0;
+    bh->nsampled = v[6] + v[7] + v[8] + v[9];
+    bh->sample_next = 0;
   }
 }
 
@@ -1829,22 +1881,23 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 
 namespace chk {
 
-hipError_t launch_batch_sample(const float* xy, const uint64_t* off, uint32_t nsets,
-                               const BatchHdr* bh, SamplePoly* polys, uint32_t sample_min,
+hipError_t launch_batch_sample(const float* xy, const uint64_t* off, BatchHdr* bh,
+                               const uint32_t* slist, SamplePoly* polys, uint32_t sample_min,
                                uint32_t grid, hipStream_t st);
 
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
-                                    uint32_t sample_grid, hipStream_t st, LaunchHook* hk) {
+                                    uint32_t sample_grid, uint32_t* slist, hipStream_t st,
+                                    LaunchHook* hk) {
   hooked(hk, "batch_plan", [&] {
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, total_points, tile, bh,
-                       sets, tiles);
+    hipLaunchKernelGGL(k_batch_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, off, nsets,
+                       total_points, tile, sample_min, bh, sets, tiles, polys, slist);
   });
   hipError_t e = hipSuccess;
   hooked(hk, "batch_sample",
-         [&] { e = launch_batch_sample(xy, off, nsets, bh, polys, sample_min, sample_grid, st); });
+         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, sample_min, sample_grid, st); });
   if (e != hipSuccess) return e;
   hooked(hk, "batch_pass", [&] {
     hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,

@@ -1570,32 +1570,48 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   }
 }
 
-// One workgroup: tiles of kHullTile candidates for every unfinished set.
+// Tiles of kHullTile candidates for every unfinished set, in set order.
+// Workgroup b owns sets b kBlock .. b kBlock + kBlock - 1, one per thread;
+// every workgroup first counts the tiles of all sets (a strided pass over
+// the set states, from L2) for the first tile of its own and the round's
+// total.
 __global__ __launch_bounds__(kBlock) void k_batch_round_plan(const uint64_t* __restrict__ off,
                                                              uint32_t nsets,
                                                              BatchHdr* __restrict__ bh,
                                                              SetState* __restrict__ sets,
                                                              int stage,
                                                              SetTile* __restrict__ rtiles) {
-  const uint32_t per = (nsets + kBlock - 1) / kBlock;
-  const uint32_t s0 = threadIdx.x * per;
-  const uint32_t s1 = s0 + per < nsets ? s0 + per : nsets;
-  uint32_t mine = 0;
-  for (uint32_t s = s0; s < s1; ++s)
-    if (!sets[s].done) mine += (sets[s].cnt[stage] + kHullTile - 1) / kHullTile;
-  uint32_t total;
-  uint32_t t = block_excl_scan(mine, total);
-  for (uint32_t s = s0; s < s1; ++s) {
-    if (sets[s].done) continue;
-    const uint32_t a = (uint32_t)off[s], c = sets[s].cnt[stage];
-    for (uint32_t p = 0; p < c; p += kHullTile) {
-      SetTile st;
-      st.set = s; st.begin = a + p; st.end = a + (p + kHullTile < c ? p + kHullTile : c); st.pad = 0;
-      rtiles[t++] = st;
-    }
-    sets[s].cnt[stage + 1] = 0;
+  __shared__ uint32_t s_red[kWaves][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t first = blockIdx.x * kBlock;
+  auto tiles_of = [](uint32_t c) { return c / kHullTile + (c % kHullTile ? 1u : 0u); };
+  uint32_t before = 0, all = 0;
+  for (uint32_t s = threadIdx.x; s < nsets; s += kBlock) {
+    const uint32_t t = sets[s].done ? 0u : tiles_of(sets[s].cnt[stage]);
+    all += t;
+    before += s < first ? t : 0u;
   }
-  if (threadIdx.x == 0) bh->nround[stage] = total;
+  auto add = [](uint32_t a, uint32_t b) { return a + b; };
+  before = wave_allreduce(before, add);
+  all = wave_allreduce(all, add);
+  if (lane == 0) { s_red[w][0] = before; s_red[w][1] = all; }
+  __syncthreads();
+  before = all = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) { before += s_red[q][0]; all += s_red[q][1]; }
+  const uint32_t s = first + threadIdx.x;
+  const bool live = s < nsets && !sets[s].done;
+  const uint32_t c = live ? sets[s].cnt[stage] : 0u;
+  uint32_t unused;
+  uint32_t t = before + block_excl_scan(tiles_of(c), unused);
+  const uint32_t a = live ? (uint32_t)off[s] : 0u;
+  for (uint32_t p = 0; p < c; p += kHullTile) {
+    SetTile st;
+    st.set = s; st.begin = a + p; st.end = a + (p + kHullTile < c ? p + kHullTile : c); st.pad = 0;
+    rtiles[t++] = st;
+  }
+  if (live) sets[s].cnt[stage + 1] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) bh->nround[stage] = all;
 }
 
 // Tile hulls of one round, appended to the set's slice of the next buffer.
@@ -1729,8 +1745,8 @@ hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr*
   });
   for (int r = 0; r < kBatchRounds; ++r) {
     hooked(hk, "batch_round_plan", [&] {
-      hipLaunchKernelGGL(k_batch_round_plan, dim3(1), dim3(kBlock), 0, st, off, nsets, bh, sets, r,
-                         rtiles);
+      hipLaunchKernelGGL(k_batch_round_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, off,
+                         nsets, bh, sets, r, rtiles);
     });
     hooked(hk, "batch_round", [&] {
       hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,

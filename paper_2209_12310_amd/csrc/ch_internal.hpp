@@ -127,10 +127,12 @@ constexpr int kPolyMax = 512;              // directions (and at most vertices),
 constexpr uint32_t kLutBins = 2048;        // single set: pseudo-angle bins of the wedge table
 constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
+constexpr uint32_t kSampleRun = 16;        // consecutive points per sample run (128 bytes)
 constexpr uint32_t kSampleBlocks = kSampleN / kSamplePer;
 constexpr uint32_t kSampleMin = 1u << 17;  // ch_hull samples from this many points on
 constexpr uint32_t kBatchDirs = 256;       // batch: directions per set
 constexpr uint32_t kBatchSample = 2048;    // batch: sample points per chunk
+static_assert(kSamplePer % kSampleRun == 0 && kBatchSample % kSampleRun == 0, "whole runs");
 constexpr uint32_t kBatchChunkPoints = 131072;  // batch: one sample chunk per this many points
 constexpr uint32_t kBatchChunksMax = 4;
 constexpr uint32_t kBatchSampleMin = 1u << 15;
@@ -261,7 +263,9 @@ struct BatchHdr {
   uint32_t ntiles;                   // pass tiles (plan kernel)
   uint32_t bad_offsets;              // offsets not non-decreasing or not ending at the total
   uint32_t nround[kBatchRounds + 1]; // hull-round tiles per round
-  uint32_t pad[10];
+  uint32_t nsampled;                 // sets in the sampler's list (plan kernel)
+  uint32_t sample_next;              // next list entry a sampler workgroup takes
+  uint32_t pad[8];
 };
 
 // Per-set state, one struct per set.
@@ -276,8 +280,15 @@ struct SetState {
 };
 
 struct BatchLayout {
-  size_t hdr, sets, polys, tiles, rtiles, recA, recB, total;
+  size_t hdr, sets, polys, slist, tiles, rtiles, recA, recB, total;
 };
+
+// Sample chunks of a set of n points in batch mode (0: no sample polygon).
+__host__ __device__ inline uint32_t batch_chunks(uint64_t n, uint32_t sample_min) {
+  if (n < sample_min || n < kBatchSample) return 0;
+  const uint64_t c = n / kBatchChunkPoints;
+  return c < 1 ? 1u : (c > kBatchChunksMax ? kBatchChunksMax : (uint32_t)c);
+}
 
 inline BatchLayout batch_layout(uint32_t nsets, uint64_t total_points) {
   BatchLayout L{};
@@ -287,6 +298,7 @@ inline BatchLayout batch_layout(uint32_t nsets, uint64_t total_points) {
   L.hdr = o;    o = align_up(o + sizeof(BatchHdr), 256);
   L.sets = o;   o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SetState), 256);
   L.polys = o;  o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SamplePoly), 256);
+  L.slist = o;  o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(uint32_t), 256);
   L.tiles = o;  o = align_up(o + ntiles * sizeof(SetTile), 256);
   L.rtiles = o; o = align_up(o + nrt * sizeof(SetTile), 256);
   const size_t m = total_points ? total_points : 1;

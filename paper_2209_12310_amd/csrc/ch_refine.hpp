@@ -420,8 +420,10 @@ __device__ __forceinline__ void dir_minmax(const int2* __restrict__ sp, uint32_t
 }
 
 // Single set, before the fused pass. k_sample_dirs: workgroup b takes sample
-// points b*kSamplePer .. +kSamplePer-1 of kSampleN spread evenly over [0, n)
-// (point floor(k n / kSampleN)) and writes, per direction, its largest dot
+// points b*kSamplePer .. +kSamplePer-1 of kSampleN, taken as runs of
+// kSampleRun consecutive points spread evenly over [0, n) (run r starts at
+// floor(r n / (kSampleN / kSampleRun)); positions past the end clamp to the
+// last point) and writes, per direction, its largest dot
 // product with that point's coordinates (one partial per workgroup and
 // direction, written contiguously, no atomics). k_sample_reduce: each
 // workgroup folds the partials of kReduceDirsPerBlock directions into the
