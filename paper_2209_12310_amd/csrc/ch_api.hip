@@ -59,8 +59,8 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
-                                    uint32_t sample_grid, uint32_t* slist, hipStream_t st,
-                                    LaunchHook* hk);
+                                    uint32_t sample_grid, uint32_t* slist, uint32_t* luts,
+                                    hipStream_t st, LaunchHook* hk);
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
@@ -464,8 +464,8 @@ ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
   hipError_t e = launch_batch_filter_side(d_xy, d_off, nsets, total_points, p.tile_points, bh, sets,
                                           at<SamplePoly>(d_ws, L.polys), at<SetTile>(d_ws, L.tiles),
                                           recA, recB, p.pass_blocks, p.sample_min,
-                                          (uint32_t)ctx->cu_count * 4, at<uint32_t>(d_ws, L.slist), st,
-                                          hk);
+                                          (uint32_t)ctx->cu_count * 4, at<uint32_t>(d_ws, L.slist),
+                                          at<uint32_t>(d_ws, L.luts), st, hk);
   if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
   e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
                              d_hull_idx, d_hull_count, p.hull_blocks, st, hk);

@@ -1531,6 +1531,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restric
     for (int r = 0; r <= kBatchRounds; ++r) bh->nround[r] = 0;
     bh->nsampled = v[6] + v[7] + v[8] + v[9];
     bh->sample_next = 0;
+    bh->refine_next = 0;
   }
 }
 
@@ -1565,8 +1566,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
                                                        const SetTile* __restrict__ tiles,
                                                        SetState* __restrict__ sets,
                                                        const SamplePoly* __restrict__ polys,
+                                                       const uint32_t* __restrict__ luts,
                                                        Rec* __restrict__ cand) {
-  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
+  __shared__ int32_t s_pvx[kBatchDirs], s_pvy[kBatchDirs];
+  __shared__ uint32_t s_lut[kBatchLutBins];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
   __shared__ Rec s_cb[kWaves][kCapB];  // staged candidate records of the wave
@@ -1578,14 +1581,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
     SetState& ss = sets[st.set];
     // The set's sample polygon, if it has one (block-uniform).
     const SamplePoly* __restrict__ sp = &polys[st.set];
-    const uint32_t pnv = min(sp->nv, (uint32_t)kPolyMax);
+    const uint32_t pnv = min(sp->nv, (uint32_t)kBatchDirs);
     const bool use_sp = pnv >= 3;
     float pcx = 0.f, pcy = 0.f, pr2 = 0.f, pos = 0.f, pot = 0.f;
-    __syncthreads();  // the previous tile is done with s_pvx / s_pvy
+    int32_t pcxi = 0, pcyi = 0;
+    __syncthreads();  // the previous tile is done with s_pvx / s_pvy / s_lut
     if (use_sp) {
       for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = sp->vx[i]; s_pvy[i] = sp->vy[i]; }
-      pcx = (float)sp->cx * (1.0f / kGridF);
-      pcy = (float)sp->cy * (1.0f / kGridF);
+      const uint32_t* __restrict__ lut = luts + size_t(st.set) * kBatchLutBins;
+      for (uint32_t i = threadIdx.x; i < kBatchLutBins; i += kBlock) s_lut[i] = lut[i];
+      pcxi = sp->cx;
+      pcyi = sp->cy;
+      pcx = (float)pcxi * (1.0f / kGridF);
+      pcy = (float)pcyi * (1.0f / kGridF);
       pr2 = sp->r2;
       pos = sp->os;
       pot = sp->ot;
@@ -1629,7 +1637,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
       }
       wave_sync();
       const bool keep = lane < (int)cnt &&
-                        !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+                        !poly_lut_inside<kBatchLutBins>(s_pvx, s_pvy, pnv, s_lut, pcxi, pcyi,
+                                                        (int32_t)(x * kGridF), (int32_t)(y * kGridF));
       emit(keep, x, y, gl);
     };
     auto push = [&](bool qq, float x, float y, uint32_t gl) {
@@ -1711,8 +1720,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
         const uint32_t g = singles[i];
         const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
         keys_add(k, x, y, bad);
-        if (!use_sp ||
-            !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF)))
+        if (!use_sp || !poly_lut_inside<kBatchLutBins>(s_pvx, s_pvy, pnv, s_lut, pcxi, pcyi,
+                                                       (int32_t)(x * kGridF), (int32_t)(y * kGridF)))
           cand[base + atomicAdd(&ss.ncand, 1u)] = make_payload<Rec>(g - base, x, y);
       }
     }
@@ -1730,28 +1739,188 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
   }
 }
 
-// After the per-set octagons: the octagon test of every set's candidates
-// (one workgroup per set at a time), survivors appended as records to the
-// set's slice of `surv`, their count in cnt[0].
+// Candidates per set from which the batch candidates get a second polygon.
+constexpr uint32_t kRefineMin = 1024;
+
+// Whole workgroup, one set's m >= kRefineMin candidates (every point not
+// strictly inside its sample polygon, or all its points) and a point c
+// inside its hull: a second polygon from the candidates themselves. The plane around c is cut
+// into kBatchDirs bins of pseudo-angle; in each bin the candidate of largest
+// dot product with the bin's middle direction is kept (a 64-bit LDS max of
+// (dot product, position)), and the kept points, in bin order, go through
+// build_poly (repeats and reflex points dropped until none is left, then the
+// same exact checks as any polygon), which overwrites the set's SamplePoly
+// and wedge table. Every vertex is an input point, so a candidate strictly
+// inside the result is not a hull vertex whichever points were picked; a
+// failed check leaves nv = 0. When the candidates hold most of the set's
+// points near the hull (points close to a circle), the kept points are the
+// set's extreme points in the bins' directions, and the second polygon is
+// as close to the hull as its number of sides allows.
+__device__ void refine_poly(const Rec* __restrict__ cand, uint32_t m, int32_t cx, int32_t cy,
+                            SamplePoly* __restrict__ out, uint32_t* __restrict__ lut) {
+  static_assert(kBatchDirs == (uint32_t)kBlock, "one bin per thread");
+  __shared__ uint64_t s_bin[kBatchDirs];
+  __shared__ int32_t s_da[kBatchDirs], s_db[kBatchDirs];
+  __shared__ int32_t s_px[kBatchDirs], s_py[kBatchDirs];
+  {
+    // Bin k: pseudo-angles [4k, 4k + 4) / kBatchDirs; its middle direction as
+    // an integer vector with |a| + |b| = 1024 (dot products below 2^30).
+    const uint32_t k = threadIdx.x;
+    const float pa = ((float)k + 0.5f) * (4.0f / (float)kBatchDirs);
+    const uint32_t q = (uint32_t)pa;
+    const int32_t f = (int32_t)__builtin_rintf((pa - (float)q) * 1024.0f);
+    const int32_t u = 1024 - f, v = f;
+    s_da[k] = q == 0 ? u : (q == 1 ? -v : (q == 2 ? -u : v));
+    s_db[k] = q == 0 ? v : (q == 1 ? u : (q == 2 ? -v : -u));
+    s_bin[k] = 0ull;
+  }
+  __syncthreads();
+  constexpr int kR = 8;  // records per thread and step, loaded together
+  for (uint32_t i0 = threadIdx.x; i0 < m; i0 += kBlock * kR) {
+    Rec r[kR];
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * kBlock;
+      r[j] = cand[i < m ? i : m - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * kBlock;
+      const float dx = (float)(r[j].x - cx), dy = (float)(r[j].y - cy);
+      if (i >= m || (dx == 0.f && dy == 0.f)) continue;
+      const uint32_t k = min((uint32_t)(pangle32(dx, dy) * (float)(kBatchDirs / 4)), kBatchDirs - 1);
+      const int32_t dot = __mul24(s_da[k], r[j].x) + __mul24(s_db[k], r[j].y) + (1 << 30);
+      atomicMax(&s_bin[k], ((uint64_t)(uint32_t)dot << 32) | i);
+    }
+  }
+  __syncthreads();
+  const uint64_t key = s_bin[threadIdx.x];
+  uint32_t mp;
+  const uint32_t pos = block_excl_scan(key ? 1u : 0u, mp);
+  if (key) {
+    const Rec r = cand[(uint32_t)key];
+    s_px[pos] = r.x;
+    s_py[pos] = r.y;
+  }
+  __syncthreads();
+  build_poly<kBatchLutBins, 16>(s_px, s_py, mp, out, lut);
+}
+
+// Tiles of the candidates' octagon test.
+constexpr uint32_t kCandTile = 8192;
+
+// After the per-set octagons: the second polygon of every set with at least
+// kRefineMin candidates (refine_poly), one workgroup per set, the sets taken
+// through a shared counter. Its centre for the bins: the sample polygon's
+// centre, else the mean of the octagon's vertices (any point does for
+// exactness; one inside the hull gives good bins).
+__global__ __launch_bounds__(kBlock) void k_batch_refine(const uint64_t* __restrict__ off,
+                                                         uint32_t nsets, BatchHdr* __restrict__ bh,
+                                                         const SetState* __restrict__ sets,
+                                                         const Rec* __restrict__ cand,
+                                                         SamplePoly* __restrict__ polys,
+                                                         uint32_t* __restrict__ luts) {
+  __shared__ uint32_t s_item;
+  if (bh->bad_offsets) return;
+  for (;;) {
+    __syncthreads();  // the previous set is done with s_item and refine_poly's arrays
+    if (threadIdx.x == 0) s_item = atomicAdd(&bh->refine_next, 1u);
+    __syncthreads();
+    const uint32_t s = s_item;
+    if (s >= nsets) break;
+    const SetState& ss = sets[s];
+    const Octagon* __restrict__ o = &ss.oct;
+    if (off[s + 1] <= off[s] || o->status != 0 || ss.ncand < kRefineMin) continue;
+    int32_t cx = polys[s].cx, cy = polys[s].cy;
+    if (polys[s].nv < 3) {
+      int64_t sx = 0, sy = 0;
+      for (int v = 0; v < 8; ++v) { sx += o->vx[v]; sy += o->vy[v]; }
+      cx = (int32_t)(sx / 8);
+      cy = (int32_t)(sy / 8);
+    }
+    refine_poly(cand + (uint32_t)off[s], ss.ncand, cx, cy, &polys[s], luts + size_t(s) * kBatchLutBins);
+  }
+}
+
+// Tiles of kCandTile candidates of every set with a usable octagon, in set
+// order (the layout of k_batch_round_plan; the pass tiles' buffer is free
+// by now).
+__global__ __launch_bounds__(kBlock) void k_batch_cand_plan(const uint64_t* __restrict__ off,
+                                                            uint32_t nsets, BatchHdr* __restrict__ bh,
+                                                            const SetState* __restrict__ sets,
+                                                            SetTile* __restrict__ ctiles) {
+  __shared__ uint32_t s_red[kWaves][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t first = blockIdx.x * kBlock;
+  const bool bad = bh->bad_offsets != 0;
+  auto count = [&](uint32_t s) {
+    return bad || off[s + 1] <= off[s] || sets[s].oct.status != 0 ? 0u : sets[s].ncand;
+  };
+  auto tiles_of = [](uint32_t c) { return c / kCandTile + (c % kCandTile ? 1u : 0u); };
+  uint32_t before = 0, all = 0;
+  for (uint32_t s = threadIdx.x; s < nsets; s += kBlock) {
+    const uint32_t t = tiles_of(count(s));
+    all += t;
+    before += s < first ? t : 0u;
+  }
+  auto add = [](uint32_t a, uint32_t b) { return a + b; };
+  before = wave_allreduce(before, add);
+  all = wave_allreduce(all, add);
+  if (lane == 0) { s_red[w][0] = before; s_red[w][1] = all; }
+  __syncthreads();
+  before = all = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) { before += s_red[q][0]; all += s_red[q][1]; }
+  const uint32_t s = first + threadIdx.x;
+  const uint32_t c = s < nsets ? count(s) : 0u;
+  uint32_t unused;
+  uint32_t t = before + block_excl_scan(tiles_of(c), unused);
+  for (uint32_t p = 0; p < c; p += kCandTile) {
+    SetTile st;
+    st.set = s; st.begin = p; st.end = p + kCandTile < c ? p + kCandTile : c; st.pad = 0;
+    ctiles[t++] = st;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) bh->ncand_tiles = all;
+}
+
+// The octagon test of the candidates, a tile of them per workgroup at a
+// time; survivors appended as records to the set's slice of `surv`, their
+// count in cnt[0]. In a set with a second polygon (at least kRefineMin
+// candidates) a candidate strictly inside it is dropped too.
 __global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restrict__ off,
-                                                       uint32_t nsets,
                                                        const BatchHdr* __restrict__ bh,
                                                        SetState* __restrict__ sets,
+                                                       const SetTile* __restrict__ ctiles,
                                                        const Rec* __restrict__ cand,
-                                                       Rec* __restrict__ surv) {
-  if (bh->bad_offsets) return;
+                                                       Rec* __restrict__ surv,
+                                                       const SamplePoly* __restrict__ polys,
+                                                       const uint32_t* __restrict__ luts) {
+  __shared__ int32_t s_pvx[kBatchDirs], s_pvy[kBatchDirs];
+  __shared__ uint32_t s_lut[kBatchLutBins];
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
-  for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
+  const uint32_t nt = bh->ncand_tiles;
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const SetTile st = ctiles[t];
+    const uint32_t s = st.set;
     SetState& ss = sets[s];
     const Octagon* __restrict__ o = &ss.oct;
-    if (off[s + 1] <= off[s] || o->status != 0) continue;
     const uint32_t base = (uint32_t)off[s];
-    const uint32_t m = ss.ncand;
+    // Second polygon (block-uniform decision).
+    const uint32_t nv2 = ss.ncand >= kRefineMin ? min(polys[s].nv, (uint32_t)kBatchDirs) : 0u;
+    const int32_t cx2 = polys[s].cx, cy2 = polys[s].cy;
+    __syncthreads();  // the previous tile is done with s_pvx / s_pvy / s_lut
+    if (nv2 >= 3) {
+      for (uint32_t i = threadIdx.x; i < nv2; i += kBlock) { s_pvx[i] = polys[s].vx[i]; s_pvy[i] = polys[s].vy[i]; }
+      const uint32_t* __restrict__ lut = luts + size_t(s) * kBatchLutBins;
+      for (uint32_t i = threadIdx.x; i < kBatchLutBins; i += kBlock) s_lut[i] = lut[i];
+    }
+    __syncthreads();
+    const uint32_t m = st.end;
     // kR records per lane and step, loaded together; one reservation per
     // wave and step.
     constexpr int kR = 8;
-    for (uint32_t i0 = (threadIdx.x - lane) * kR; i0 < m; i0 += kBlock * kR) {
+    for (uint32_t i0 = st.begin + (threadIdx.x - lane) * kR; i0 < m; i0 += kBlock * kR) {
       Rec r[kR];
       uint64_t bk[kR];
       uint32_t tot = 0;
@@ -1763,9 +1932,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restric
 #pragma unroll
       for (int j = 0; j < kR; ++j) {
         const uint32_t i = i0 + j * 64 + lane;
-        const bool keep = i < m && classify<false>((float)r[j].x * (1.0f / kGridF),
-                                                   (float)r[j].y * (1.0f / kGridF), r[j].i, o,
-                                                   ss.vidx).keep;
+        const bool keep = i < m &&
+                          classify<false>((float)r[j].x * (1.0f / kGridF), (float)r[j].y * (1.0f / kGridF),
+                                          r[j].i, o, ss.vidx).keep &&
+                          !(nv2 >= 3 && poly_lut_inside<kBatchLutBins>(s_pvx, s_pvy, nv2, s_lut, cx2, cy2,
+                                                                       r[j].x, r[j].y));
         bk[j] = __ballot(keep);
         tot += popc64(bk[j]);
       }
@@ -1882,34 +2053,42 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 namespace chk {
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, BatchHdr* bh,
-                               const uint32_t* slist, SamplePoly* polys, uint32_t sample_min,
-                               uint32_t grid, hipStream_t st);
+                               const uint32_t* slist, SamplePoly* polys, uint32_t* luts,
+                               uint32_t sample_min, uint32_t grid, hipStream_t st);
 
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
                                     SetState* sets, SamplePoly* polys, SetTile* tiles, Rec* recs,
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
-                                    uint32_t sample_grid, uint32_t* slist, hipStream_t st,
-                                    LaunchHook* hk) {
+                                    uint32_t sample_grid, uint32_t* slist, uint32_t* luts,
+                                    hipStream_t st, LaunchHook* hk) {
   hooked(hk, "batch_plan", [&] {
     hipLaunchKernelGGL(k_batch_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, off, nsets,
                        total_points, tile, sample_min, bh, sets, tiles, polys, slist);
   });
   hipError_t e = hipSuccess;
   hooked(hk, "batch_sample",
-         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, sample_min, sample_grid, st); });
+         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, luts, sample_min, sample_grid, st); });
   if (e != hipSuccess) return e;
   hooked(hk, "batch_pass", [&] {
     hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
-                       cand);
+                       luts, cand);
   });
   hooked(hk, "batch_octagon", [&] {
     hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,
                        nsets, bh, sets);
   });
+  hooked(hk, "batch_refine", [&] {
+    hipLaunchKernelGGL(k_batch_refine, dim3(sample_grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
+                       cand, polys, luts);
+  });
+  hooked(hk, "batch_cand_plan", [&] {
+    hipLaunchKernelGGL(k_batch_cand_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, off, nsets,
+                       bh, sets, tiles);
+  });
   hooked(hk, "batch_cand", [&] {
-    hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets, cand,
-                       recs);
+    hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, bh, sets, tiles, cand, recs,
+                       polys, luts);
   });
   return hipGetLastError();
 }

@@ -125,6 +125,7 @@ struct Rec {           // a candidate hull point: grid coordinates + index
 // inner grid point, then exactly.
 constexpr int kPolyMax = 512;              // directions (and at most vertices), single set
 constexpr uint32_t kLutBins = 2048;        // single set: pseudo-angle bins of the wedge table
+constexpr uint32_t kBatchLutBins = 1024;   // batch: wedge-table bins per set
 constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
 constexpr uint32_t kSampleRun = 16;        // consecutive points per sample run (128 bytes)
@@ -265,7 +266,9 @@ struct BatchHdr {
   uint32_t nround[kBatchRounds + 1]; // hull-round tiles per round
   uint32_t nsampled;                 // sets in the sampler's list (plan kernel)
   uint32_t sample_next;              // next list entry a sampler workgroup takes
-  uint32_t pad[8];
+  uint32_t refine_next;              // next set a second-polygon workgroup takes
+  uint32_t ncand_tiles;              // tiles of the candidates' octagon test
+  uint32_t pad[6];
 };
 
 // Per-set state, one struct per set.
@@ -280,7 +283,7 @@ struct SetState {
 };
 
 struct BatchLayout {
-  size_t hdr, sets, polys, slist, tiles, rtiles, recA, recB, total;
+  size_t hdr, sets, polys, luts, slist, tiles, rtiles, recA, recB, total;
 };
 
 // Sample chunks of a set of n points in batch mode (0: no sample polygon).
@@ -298,6 +301,7 @@ inline BatchLayout batch_layout(uint32_t nsets, uint64_t total_points) {
   L.hdr = o;    o = align_up(o + sizeof(BatchHdr), 256);
   L.sets = o;   o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SetState), 256);
   L.polys = o;  o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(SamplePoly), 256);
+  L.luts = o;   o = align_up(o + size_t(nsets ? nsets : 1) * kBatchLutBins * sizeof(uint32_t), 256);
   L.slist = o;  o = align_up(o + size_t(nsets ? nsets : 1) * sizeof(uint32_t), 256);
   L.tiles = o;  o = align_up(o + ntiles * sizeof(SetTile), 256);
   L.rtiles = o; o = align_up(o + nrt * sizeof(SetTile), 256);

@@ -68,8 +68,9 @@ __device__ __forceinline__ float pangle32(float dx, float dy) {
 // Wedge table of a polygon about its centre c: the vertices, in
 // counter-clockwise order starting at the smallest pseudo-angle, split the
 // plane around c into wedges (wedge j between vertices j and j+1, the last
-// one wrapping through angle 0). Bin k of kLutBins covers the pseudo-angles
-// [k w - eps, (k+1) w + eps], w = 4 / kLutBins, eps = 2^-16 (far above the
+// one wrapping through angle 0). Bin k of Bins (kLutBins for one set,
+// kBatchLutBins per batch set) covers the pseudo-angles
+// [k w - eps, (k+1) w + eps], w = 4 / Bins, eps = 2^-16 (far above the
 // error of pangle32); its entry holds the first wedge meeting that interval
 // (low 16 bits) and the number of consecutive wedges that do (high 16 bits).
 constexpr double kLutEps = 0x1p-16;
@@ -79,13 +80,14 @@ constexpr double kLutEps = 0x1p-16;
 // of the side of the wedge its direction from c falls in; the bin of its
 // computed pseudo-angle lists that wedge (the error is below eps), so testing
 // the listed sides decides. c itself is strictly inside.
+template <uint32_t Bins = kLutBins>
 __device__ __forceinline__ bool poly_lut_inside(const int32_t* vx, const int32_t* vy, uint32_t nv,
                                                 const uint32_t* lut, int32_t cx, int32_t cy,
                                                 int32_t px, int32_t py) {
   const float dx = (float)(px - cx), dy = (float)(py - cy);
   if (dx == 0.f && dy == 0.f) return true;
   const float th = pangle32(dx, dy);
-  const uint32_t k = min((uint32_t)(th * (float)(kLutBins / 4)), kLutBins - 1);
+  const uint32_t k = min((uint32_t)(th * (float)(Bins / 4)), Bins - 1);
   const uint32_t e = lut[k];
   uint32_t j = e & 0xffffu;
   bool in = true;
@@ -187,7 +189,8 @@ __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_
 // Whole workgroup. px/py[0..m0) (LDS) hold the extreme points in direction
 // order; writes the SamplePoly, and with lut != null its wedge table. Steps:
 // drop repeats of the previous point (cyclically), drop points where the
-// boundary does not turn left, then verify and measure in wave 0: every turn
+// boundary does not turn left (for up to Passes rounds), then verify and
+// measure in wave 0: every turn
 // strictly left, the centre c strictly left of every side, exactly one side
 // crossing the line y = c.y upwards (one turn around c); r2 = the squared
 // distance from c to the nearest side line, rounded down with a relative
@@ -195,6 +198,7 @@ __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_
 // the vertices are stored from the one of
 // smallest pseudo-angle about c on; a sequence of pseudo-angles that does not
 // wrap exactly once disables the polygon.
+template <uint32_t Bins = kLutBins, int Passes = 1>
 __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SamplePoly* __restrict__ out,
                                   uint32_t* __restrict__ lut = nullptr) {
   __shared__ int32_t qx[kPolyMax], qy[kPolyMax];
@@ -216,21 +220,31 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
   for (uint32_t e = 0; e < E; ++e)
     if (keep & (1u << e)) { qx[pos] = px[j0 + e]; qy[pos] = py[j0 + e]; ++pos; }
   __syncthreads();
-  // 2. collinear or reflex points
-  const uint32_t E1 = (m1 + kBlock - 1) / kBlock;
-  const uint32_t i0 = threadIdx.x * E1;
-  keep = 0; nk = 0;
-  for (uint32_t e = 0; e < E1 && m1 >= 3; ++e) {
-    const uint32_t i = i0 + e;
-    if (i < m1) {
-      const uint32_t p = i ? i - 1 : m1 - 1, q = i + 1 < m1 ? i + 1 : 0;
-      if (orient64(qx[p], qy[p], qx[i], qy[i], qx[q], qy[q]) > 0) { keep |= 1u << e; ++nk; }
+  // 2. collinear or reflex points, for up to Passes rounds (dropping a point
+  //    can make a neighbour reflex; the rounds stop once one drops none)
+  uint32_t m = m1;
+  for (int it = 0; it < Passes; ++it) {
+    if (it) {
+      if (m == m1 || m < 3) break;
+      for (uint32_t j = threadIdx.x; j < m; j += kBlock) { qx[j] = px[j]; qy[j] = py[j]; }
+      __syncthreads();
+      m1 = m;
     }
+    const uint32_t E1 = (m1 + kBlock - 1) / kBlock;
+    const uint32_t i0 = threadIdx.x * E1;
+    keep = 0; nk = 0;
+    for (uint32_t e = 0; e < E1 && m1 >= 3; ++e) {
+      const uint32_t i = i0 + e;
+      if (i < m1) {
+        const uint32_t p = i ? i - 1 : m1 - 1, q = i + 1 < m1 ? i + 1 : 0;
+        if (orient64(qx[p], qy[p], qx[i], qy[i], qx[q], qy[q]) > 0) { keep |= 1u << e; ++nk; }
+      }
+    }
+    pos = block_excl_scan(nk, m);
+    for (uint32_t e = 0; e < E1; ++e)
+      if (keep & (1u << e)) { px[pos] = qx[i0 + e]; py[pos] = qy[i0 + e]; ++pos; }
+    if (Passes > 1) __syncthreads();
   }
-  uint32_t m;
-  pos = block_excl_scan(nk, m);
-  for (uint32_t e = 0; e < E1; ++e)
-    if (keep & (1u << e)) { px[pos] = qx[i0 + e]; py[pos] = qy[i0 + e]; ++pos; }
   __syncthreads();
   // 3. verify, centre, disc. The centre is the polygon's area centroid
   //    (interior for a convex polygon; computed in fp64 relative to vertex
@@ -342,11 +356,11 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
   // Bin k's interval ends, looked up by a binary search over the sorted
   // vertex angles: the wedge holding an angle th is the last vertex j with
   // t_j <= th, or the wrapping wedge m-1 when th < t_0. Each thread takes
-  // kLutBins / kBlock consecutive bins and runs their searches in lockstep
+  // Bins / kBlock consecutive bins and runs their searches in lockstep
   // (independent LDS reads in flight together).
-  constexpr uint32_t kQ = kLutBins / kBlock;
-  static_assert(kLutBins % kBlock == 0, "whole bins per thread");
-  constexpr double w = 4.0 / (double)kLutBins;
+  constexpr uint32_t kQ = Bins / kBlock;
+  static_assert(Bins % kBlock == 0, "whole bins per thread");
+  constexpr double w = 4.0 / (double)Bins;
   if (use) {
     double th[2 * kQ];
     uint32_t pos[2 * kQ];
