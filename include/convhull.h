@@ -159,7 +159,11 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
  * used the sample polygon, bit 1 when its inner region was the octagon (else
  * the disc), bit 2 when it streamed on its whole grid (many points outside
  * the inner region) rather than one workgroup per CU; 0 without a single
- * read. Diagnostics only. */
+ * read; and the records left by the second polygon, built from the
+ * survivors when one workgroup could not take them all (0 when it did not
+ * run; then the rounds and the large-hull path start from those). Not in
+ * the paper: a refinement of Alg. 1's filter stage, exact like it.
+ * Diagnostics only. */
 typedef struct {
   uint32_t n;
   uint32_t candidates;
@@ -168,6 +172,7 @@ typedef struct {
   uint32_t large_path;
   uint32_t h;
   uint32_t single_read;
+  uint32_t refined;
 } ch_hull_info;
 ch_status ch_last_hull_info(const ch_ctx* ctx, ch_hull_info* out);
 

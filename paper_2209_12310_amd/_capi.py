@@ -52,7 +52,7 @@ class BatchParams(ctypes.Structure):
 class HullInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("candidates", ctypes.c_uint32), ("survivors", ctypes.c_uint32),
                 ("rounds", ctypes.c_uint32), ("large_path", ctypes.c_uint32), ("h", ctypes.c_uint32),
-                ("single_read", ctypes.c_uint32)]
+                ("single_read", ctypes.c_uint32), ("refined", ctypes.c_uint32)]
 
 
 class ServeConfig(ctypes.Structure):

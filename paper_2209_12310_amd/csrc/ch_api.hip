@@ -27,8 +27,10 @@ hipError_t launch_oct_build(const double* partials, const uint32_t* part_bad, ui
                             Header* hdr, Result* res, uint64_t* tstat, uint32_t ntstat,
                             hipStream_t st);
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
-                              uint32_t* count0,
-                              hipStream_t st);
+                              uint32_t* count0, RefineState* rs, hipStream_t st);
+hipError_t launch_refine(const Rec* in, const uint32_t* count_in, uint32_t max_in,
+                         const SamplePoly* poly, const Octagon* oct, RefineState* rs, Rec* out,
+                         uint32_t max_blocks, hipStream_t st, LaunchHook* hk);
 hipError_t launch_pass_hull(const float* xy, uint32_t n, uint32_t head, double* partials,
                             uint32_t* part_bad, const SamplePoly* poly, Rec* cand, void* scratch,
                             uint32_t blocks, uint32_t narrow_blocks, hipStream_t st);
@@ -115,6 +117,7 @@ struct ch_ctx {
   uint32_t narrow_blocks = 256;
   uint32_t large_direct = kLargeDirect;  // survivors from which ch_hull skips the tile rounds
   bool poll = true;  // watch the published status instead of waiting for the stream
+  bool second_poly = true;  // ch_hull: the second polygon when one workgroup cannot take the survivors
   unsigned char* pinned = nullptr;  // kResBytes + 4 * kPinIdx
   unsigned char* pinned_dev = nullptr;  // its device address (null: copied, not written directly)
   void* noalloc_ws = nullptr;           // device address of `scratch` on this context's device
@@ -274,7 +277,7 @@ ch_status run_filter(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* surv,
   if (fused) {
     {
       ProfScope p(ctx, st, "sample_poly");
-      e = launch_sample_poly(d_xy, n, scratch, poly, count_out, st);
+      e = launch_sample_poly(d_xy, n, scratch, poly, count_out, at<RefineState>(ws, L.refine), st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "sample polygon launch");
     {
@@ -535,6 +538,7 @@ ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** ou
     if (v >= 1 && v <= kReduceMaxBlocks) ctx->narrow_blocks = (uint32_t)v;
   }
   if (const char* e = std::getenv("CH_HULL_WAIT")) ctx->poll = std::strcmp(e, "stream") != 0;
+  if (const char* e = std::getenv("CH_SECOND_POLY")) ctx->second_poly = std::strcmp(e, "0") != 0;
   if (const char* e = std::getenv("CH_LARGE_DIRECT")) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= kFinalTile && v <= (long)CH_MAX_POINTS) ctx->large_direct = (uint32_t)v;
@@ -728,6 +732,36 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   // The survivors: the octagon test's output, or the candidate records
   // themselves (list B) when the test was skipped.
   const Rec* surv0 = hres->cand_surv ? rec[1] : srec;
+  const uint32_t* cnt0 = &hdr->count;
+  // Too many survivors for one workgroup after the refined filter, but not
+  // so many that the large-hull path (whose cost is mostly fixed) would
+  // beat the extra steps: the second polygon from the survivors themselves
+  // (k_refine_bins), the survivors strictly inside it dropped, and the block
+  // hull again. The kept records go to whichever of the survivor and
+  // candidate lists the survivors do not occupy (list A stays free for the
+  // rounds).
+  if (hres->status == RES_MORE && hres->cin <= kRefineMaxSingle && n >= kSampleMin &&
+      ctx->second_poly) {
+    RefineState* rs = at<RefineState>(d_ws, L.refine);
+    Rec* kept = surv0 == srec ? rec[1] : srec;
+    {
+      ProfHook hook(ctx, st);
+      e = launch_refine(surv0, cnt0, hres->cin, at<SamplePoly>(d_ws, L.poly), &hdr->oct, rs, kept,
+                        (uint32_t)ctx->cu_count * 2, st, ctx->prof ? &hook : nullptr);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "second polygon launch");
+    arm_final();
+    {
+      ProfScope p(ctx, st, "hull_final");
+      e = launch_hull_final(kept, &rs->cnt, res, res_idx, &hdr->oct, dres_host, didx_host, pin_n, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hull final launch");
+    if ((e = wait_final()) != hipSuccess) return hip_fail(ctx, e, "hull final");
+    prof_collect(ctx, st);
+    surv0 = kept;
+    cnt0 = &rs->cnt;
+    info.refined = hres->cin;
+  }
   // Many survivors (points near a smooth boundary keep about half of every
   // tile hull): straight to the large-hull path.
   if (hres->status == RES_MORE && hres->cin > ctx->large_direct) large = true;
@@ -738,7 +772,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     const uint32_t gmax = (uint32_t)ctx->cu_count * 3;
     if (grid > gmax) grid = gmax;
     if (grid < 1) grid = 1;
-    const uint32_t* in_count = round == 0 ? &hdr->count : &res->round_cnt[round];
+    const uint32_t* in_count = round == 0 ? cnt0 : &res->round_cnt[round];
     {
       ProfScope p(ctx, st, round == 0 ? "hull_round0" : "hull_round");
       e = launch_hull_round(grid, round ? rec[(round - 1) & 1] : surv0, in_count, rec[round & 1],
@@ -770,7 +804,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
     // input: the last round's output, or the survivors when no round ran
     const uint32_t cin = round ? hres->round_cnt[round] : hres->cin;
     const Rec* lin = round ? rec[last_list] : surv0;
-    const uint32_t* lcnt = round ? &res->round_cnt[round] : &hdr->count;
+    const uint32_t* lcnt = round ? &res->round_cnt[round] : cnt0;
     {
       // Per-kernel events of the large-hull path when profiling is on.
       ProfHook hook(ctx, st);

@@ -128,24 +128,40 @@ constexpr uint32_t kLutBins = 2048;        // single set: pseudo-angle bins of t
 constexpr uint32_t kBatchLutBins = 1024;   // batch: wedge-table bins per set
 constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
-constexpr uint32_t kSampleRun = 16;        // consecutive points per sample run (128 bytes)
+constexpr uint32_t kSampleRun = 16;        // batch: consecutive points per sample run (128 bytes)
 constexpr uint32_t kSampleBlocks = kSampleN / kSamplePer;
 constexpr uint32_t kSampleMin = 1u << 17;  // ch_hull samples from this many points on
 constexpr uint32_t kBatchDirs = 256;       // batch: directions per set
 constexpr uint32_t kBatchSample = 2048;    // batch: sample points per chunk
-static_assert(kSamplePer % kSampleRun == 0 && kBatchSample % kSampleRun == 0, "whole runs");
+static_assert(kBatchSample % kSampleRun == 0, "whole runs");
 constexpr uint32_t kBatchChunkPoints = 131072;  // batch: one sample chunk per this many points
 constexpr uint32_t kBatchChunksMax = 4;
 constexpr uint32_t kBatchSampleMin = 1u << 15;
 
-struct SamplePoly {
+template <uint32_t V>
+struct SamplePolyT {
   uint32_t nv;         // vertex count; below 3 the polygon is not used
   int32_t cx, cy;      // grid point strictly inside the polygon
   float r2;            // squared radius (float units) of a disc about (cx, cy) inside
                        // the polygon, rounded down with a margin for fp32 tests
   float os, ot;        // octagon |dx| <= os, |dy| <= os, |dx| + |dy| <= ot (float
                        // units) about (cx, cy) inside the polygon; 0 when none
-  int32_t vx[kPolyMax], vy[kPolyMax];  // counter-clockwise, strictly convex
+  int32_t vx[V], vy[V];  // counter-clockwise, strictly convex
+};
+using SamplePoly = SamplePolyT<kPolyMax>;
+
+// Single set, second polygon from the survivors (see k_refine_bins):
+// bins, vertex capacity, wedge-table bins.
+constexpr uint32_t kRefineBins = 1024;
+constexpr uint32_t kRefineLut = 2048;
+constexpr uint32_t kRefineMaxSingle = 1u << 18;  // more survivors: straight to the large-hull path
+struct RefineState {
+  uint64_t bin[kRefineBins];  // (dot product, record) maxima per bin; zero between calls
+  uint32_t arrive;            // workgroups of k_refine_bins done; zero between calls
+  uint32_t cnt;               // records kept by k_refine_filter
+  uint32_t pad[62];
+  SamplePolyT<kRefineBins> poly;
+  uint32_t lut[kRefineLut];
 };
 
 constexpr size_t kHdrBytes = 1024;
@@ -160,7 +176,7 @@ constexpr uint32_t hull_cap(uint32_t n) { return n < kHullCapMax ? (n ? n : 1u) 
 // Workspace layout. ch_filter uses the prefix up to `filter_end`.
 struct Layout {
   size_t hdr, res, res_idx, partials, part_bad, tstat, staging, filter_end;
-  size_t surv, recA, recB, phist, ptot, lstA, lstB, wcnt, poly, samp, total;
+  size_t surv, recA, recB, phist, ptot, lstA, lstB, wcnt, poly, samp, refine, total;
 };
 
 constexpr Layout layout(uint32_t n) {
@@ -181,7 +197,7 @@ constexpr Layout layout(uint32_t n) {
   L.recA = o;      o = align_up(o + m * sizeof(Rec), 256);
   L.recB = o;      o = align_up(o + m * sizeof(Rec), 256);
   if (n <= (uint32_t)kFinalTile) {  // one workgroup: no rounds, no large-hull path
-    L.phist = L.ptot = L.lstA = L.lstB = L.wcnt = L.poly = L.samp = o;
+    L.phist = L.ptot = L.lstA = L.lstB = L.wcnt = L.poly = L.samp = L.refine = o;
     L.total = o;
     return L;
   }
@@ -193,10 +209,12 @@ constexpr Layout layout(uint32_t n) {
   L.lstA = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
   L.lstB = o;      o = align_up(o + 2 * kLargeListCap * sizeof(Rec), 256);
   L.wcnt = o;      o = align_up(o + 2 * size_t(kChunks + kGroups) * 4, 256);
-  // Refined filter: the sample polygon and the direction maxima.
+  // Refined filter: the sample polygon and the direction maxima, then the
+  // second polygon's state.
   L.poly = o;      o = align_up(o + sizeof(SamplePoly), 256);
   L.samp = o;      o = align_up(o + size_t(kPolyMax) * 8 + 256 + size_t(kLutBins) * 4 +
                                        size_t(kSampleBlocks) * kPolyMax * 16, 256);
+  L.refine = o;    o = align_up(o + sizeof(RefineState), 256);
   L.total = o;
   return L;
 }

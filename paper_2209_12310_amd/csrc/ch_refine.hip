@@ -171,19 +171,21 @@ static_assert(sizeof(SampleDirs) <= size_t(kPolyMax) * 8 + 256 + size_t(kLutBins
 
 __global__ __launch_bounds__(kBlock) void k_sample_dirs(const float* __restrict__ xy, uint32_t n,
                                                         SampleDirs* __restrict__ sd,
-                                                        uint32_t* __restrict__ count0) {
+                                                        uint32_t* __restrict__ count0,
+                                                        RefineState* __restrict__ rs) {
   static_assert(kPolyMax == 2 * kBlock, "a direction and its opposite per thread");
+  static_assert(kRefineBins == 4 * kSampleBlocks, "four second-polygon bins cleared per workgroup");
   __shared__ int2 sp[kSamplePer];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sd->arrive = 0;  // for k_sample_reduce
     sd->cand = 0;    // for the fused pass
     *count0 = 0;     // survivors of the candidates' octagon test, two launches on
+    rs->arrive = 0;  // for k_refine_bins
   }
-  constexpr uint32_t kRunsAll = kSampleN / kSampleRun, kRunsPer = kSamplePer / kSampleRun;
-  for (uint32_t q = threadIdx.x; q < kSamplePer; q += kBlock) {
-    const uint64_t r = uint64_t(blockIdx.x) * kRunsPer + q / kSampleRun;
-    sp[q] = grid_point(xy, (size_t)min<uint64_t>((r * n) / kRunsAll + q % kSampleRun, n - 1));
-  }
+  if (threadIdx.x < 4) rs->bin[4 * blockIdx.x + threadIdx.x] = 0ull;
+  const uint32_t k0 = blockIdx.x * kSamplePer;
+  for (uint32_t q = threadIdx.x; q < kSamplePer; q += kBlock)
+    sp[q] = grid_point(xy, (size_t)((uint64_t(k0 + q) * n) / kSampleN));
   __syncthreads();
   const uint32_t d = threadIdx.x;
   int32_t a, b;
@@ -240,10 +242,197 @@ __global__ __launch_bounds__(kBlock) void k_sample_reduce(const float* __restric
   build_poly(px, py, kPolyMax, poly, sd->lut);
 }
 
+// Single set, when the block hull finds too many survivors: a second
+// polygon from the survivor records themselves. The plane around c (the
+// sample polygon's centre, else the mean of the octagon's vertices) is cut
+// into kRefineBins bins of pseudo-angle; per bin the record of largest dot
+// product with the bin's middle direction is kept: each workgroup takes the
+// maxima of (dot product, record) over its records in LDS and folds its
+// non-empty bins into rs->bin with 64-bit atomic max. The last workgroup to
+// arrive gathers the kept records in bin order, clears the bins and the
+// counter for the next call, and builds the polygon and its wedge table with
+// build_poly (repeats and reflex points dropped until none remain). Every
+// vertex is an input point, so a record strictly inside it is not a hull
+// vertex, whichever records were kept; a failed check leaves nv = 0. For
+// points near a smooth curve the kept records are the extreme points in the
+// bins' directions, and the polygon is as close to the hull as its number of
+// sides allows. Clears rs->cnt for k_refine_filter.
+__global__ __launch_bounds__(kBlock) void k_refine_bins(const Rec* __restrict__ in,
+                                                        const uint32_t* __restrict__ count_in,
+                                                        const SamplePoly* __restrict__ poly,
+                                                        const Octagon* __restrict__ oct,
+                                                        RefineState* __restrict__ rs) {
+  constexpr uint32_t B = kRefineBins, E = B / kBlock;
+  static_assert(B % kBlock == 0, "whole bins per thread");
+  __shared__ uint64_t s_bin[B];
+  __shared__ int32_t s_da[B], s_db[B];
+  __shared__ uint32_t s_last;
+  const uint32_t m = *count_in;
+  int32_t cx = poly->cx, cy = poly->cy;
+  if (poly->nv < 3) {
+    int64_t sx = 0, sy = 0;
+    for (int v = 0; v < 8; ++v) { sx += oct->vx[v]; sy += oct->vy[v]; }
+    cx = (int32_t)(sx / 8);
+    cy = (int32_t)(sy / 8);
+  }
+  // Bin k: pseudo-angles [4k, 4k + 4) / B; its middle direction as an
+  // integer vector with |a| + |b| = 1024 (dot products below 2^30).
+  for (uint32_t k = threadIdx.x; k < B; k += kBlock) {
+    const float pa = ((float)k + 0.5f) * (4.0f / (float)B);
+    const uint32_t q = (uint32_t)pa;
+    const int32_t f = (int32_t)__builtin_rintf((pa - (float)q) * 1024.0f);
+    const int32_t u = 1024 - f, v = f;
+    s_da[k] = q == 0 ? u : (q == 1 ? -v : (q == 2 ? -u : v));
+    s_db[k] = q == 0 ? v : (q == 1 ? u : (q == 2 ? -v : -u));
+    s_bin[k] = 0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) rs->cnt = 0;
+  __syncthreads();
+  constexpr int kR = 16;  // records per thread and step, loaded together
+  const uint32_t stride = gridDim.x * kBlock * kR;
+  for (uint32_t i0 = blockIdx.x * kBlock * kR + threadIdx.x; i0 < m; i0 += stride) {
+    Rec r[kR];
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * kBlock;
+      r[j] = in[i < m ? i : m - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * kBlock;
+      const float dx = (float)(r[j].x - cx), dy = (float)(r[j].y - cy);
+      if (i >= m || (dx == 0.f && dy == 0.f)) continue;
+      const uint32_t k = min((uint32_t)(pangle32(dx, dy) * (float)(B / 4)), B - 1);
+      const int32_t dot = __mul24(s_da[k], r[j].x) + __mul24(s_db[k], r[j].y) + (1 << 30);
+      atomicMax(&s_bin[k], ((uint64_t)(uint32_t)dot << 32) | i);
+    }
+  }
+  __syncthreads();
+  // Only bins that beat the value seen now go to the atomic (the launcher
+  // keeps the grid small: every workgroup folds up to kRefineBins bins).
+  for (uint32_t k = threadIdx.x; k < B; k += kBlock) {
+    const uint64_t v = s_bin[k];
+    if (v && v > __hip_atomic_load(&rs->bin[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax((unsigned long long*)&rs->bin[k], (unsigned long long)v);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(&rs->arrive, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // Thread t takes bins tE .. tE + E - 1 (bin order kept by the scan).
+  uint64_t key[E];
+  uint32_t nk = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    const uint32_t k = threadIdx.x * E + e;
+    key[e] = __hip_atomic_load(&rs->bin[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    nk += key[e] ? 1u : 0u;
+    rs->bin[k] = 0ull;
+  }
+  if (threadIdx.x == 0) rs->arrive = 0;
+  uint32_t mp;
+  uint32_t pos = block_excl_scan(nk, mp);  // its barriers: every thread is done with s_da / s_db
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    if (key[e]) {
+      const Rec r = in[(uint32_t)key[e]];
+      s_da[pos] = r.x;
+      s_db[pos] = r.y;
+      ++pos;
+    }
+  }
+  __syncthreads();
+  build_poly<kRefineLut, 16, kRefineBins>(s_da, s_db, mp, &rs->poly, rs->lut);
+}
+
+// The records not strictly inside the second polygon (all of them when it
+// failed its checks), in any order, with one reservation per wave and step;
+// their count in rs->cnt.
+__global__ __launch_bounds__(kBlock) void k_refine_filter(const Rec* __restrict__ in,
+                                                          const uint32_t* __restrict__ count_in,
+                                                          RefineState* __restrict__ rs,
+                                                          Rec* __restrict__ out) {
+  __shared__ int32_t s_vx[kRefineBins], s_vy[kRefineBins];
+  __shared__ uint32_t s_lut[kRefineLut];
+  const uint32_t m = *count_in;
+  const uint32_t nv = min(rs->poly.nv, kRefineBins);
+  const int32_t cx = rs->poly.cx, cy = rs->poly.cy;
+  if (nv >= 3) {
+    for (uint32_t i = threadIdx.x; i < nv; i += kBlock) { s_vx[i] = rs->poly.vx[i]; s_vy[i] = rs->poly.vy[i]; }
+    for (uint32_t i = threadIdx.x; i < kRefineLut; i += kBlock) s_lut[i] = rs->lut[i];
+  }
+  __syncthreads();
+  __shared__ uint32_t s_w[kWaves], s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  constexpr int kR = 8;  // records per lane and step, loaded together
+  // Workgroup b takes the contiguous records [b m / G, (b + 1) m / G) in
+  // steps of kBlock kR, with one reservation per step.
+  const uint32_t r0 = (uint32_t)((uint64_t)blockIdx.x * m / gridDim.x);
+  const uint32_t r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * m / gridDim.x);
+  for (uint32_t s0 = r0; s0 < r1; s0 += kBlock * kR) {
+    const uint32_t i0 = s0 + w * 64 * kR;
+    Rec r[kR];
+    uint64_t bk[kR];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * 64 + lane;
+      r[j] = i < r1 ? in[i] : Rec{};
+    }
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const uint32_t i = i0 + j * 64 + lane;
+      const bool keep = i < r1 && !(nv >= 3 && poly_lut_inside<kRefineLut>(s_vx, s_vy, nv, s_lut, cx, cy,
+                                                                           r[j].x, r[j].y));
+      bk[j] = __ballot(keep);
+      tot += popc64(bk[j]);
+    }
+    if (lane == 0) s_w[w] = tot;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      before += q < w ? s_w[q] : 0u;
+      all += s_w[q];
+    }
+    if (threadIdx.x == 0 && all) s_base = atomicAdd(&rs->cnt, all);
+    __syncthreads();
+    uint32_t p = s_base + before;
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      if ((bk[j] >> lane) & 1ull) out[p + popc64(bk[j] & lt)] = r[j];
+      p += popc64(bk[j]);
+    }
+    __syncthreads();  // s_w and s_base are rewritten next step
+  }
+}
+
+hipError_t launch_refine(const Rec* in, const uint32_t* count_in, uint32_t max_in,
+                         const SamplePoly* poly, const Octagon* oct, RefineState* rs, Rec* out,
+                         uint32_t max_blocks, hipStream_t st, LaunchHook* hk) {
+  // Bins: a workgroup per 4096 records (one step each), at most 128 (each
+  // folds its bins into the shared ones with atomics, so not many); the
+  // test: a workgroup per 2048 records, at most max_blocks.
+  uint32_t gb = (max_in + 4095) / 4096;
+  gb = gb < 1 ? 1 : (gb > 128 ? 128 : gb);
+  uint32_t g = (max_in + 2047) / 2048;
+  g = g < 1 ? 1 : (g > max_blocks ? max_blocks : g);
+  hooked(hk, "refine_bins", [&] {
+    hipLaunchKernelGGL(k_refine_bins, dim3(gb), dim3(kBlock), 0, st, in, count_in, poly, oct, rs);
+  });
+  hooked(hk, "refine_filter", [&] {
+    hipLaunchKernelGGL(k_refine_filter, dim3(g), dim3(kBlock), 0, st, in, count_in, rs, out);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, SamplePoly* poly,
-                              uint32_t* count0, hipStream_t st) {
+                              uint32_t* count0, RefineState* rs, hipStream_t st) {
   SampleDirs* sd = static_cast<SampleDirs*>(scratch);
-  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd, count0);
+  hipLaunchKernelGGL(k_sample_dirs, dim3(kSampleBlocks), dim3(kBlock), 0, st, xy, n, sd, count0, rs);
   hipLaunchKernelGGL(k_sample_reduce, dim3(kSampleReduceBlocks), dim3(kBlock), 0, st, xy, n, sd, poly);
   return hipGetLastError();
 }

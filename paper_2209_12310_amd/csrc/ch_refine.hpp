@@ -109,11 +109,12 @@ __device__ __forceinline__ bool poly_lut_inside(const int32_t* vx, const int32_t
 // 4 s^2 - 2 (2 s - t)^2 wins. The
 // float values are checked against every side in exact arithmetic (products
 // of a float and an integer below 2^21 are exact in fp64); a failure drops
-// the octagon. mx/my: LDS scratch of kPolyMax int32 each.
+// the octagon. mx/my: LDS scratch of V int32 each.
+template <uint32_t V>
 __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_t m, int32_t cx,
-                                   int32_t cy, int32_t* mx, int32_t* my, SamplePoly* __restrict__ out) {
+                                   int32_t cy, int32_t* mx, int32_t* my, SamplePolyT<V>* __restrict__ out) {
   constexpr int kCand = 8;
-  __shared__ double s_o[kPolyMax];
+  __shared__ double s_o[V];
   __shared__ double s_red[kWaves][kCand];
   __shared__ double s_smax[kWaves];
   __shared__ uint32_t s_fail;
@@ -198,10 +199,11 @@ __device__ inline void fit_octagon(const int32_t* px, const int32_t* py, uint32_
 // the vertices are stored from the one of
 // smallest pseudo-angle about c on; a sequence of pseudo-angles that does not
 // wrap exactly once disables the polygon.
-template <uint32_t Bins = kLutBins, int Passes = 1>
-__device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SamplePoly* __restrict__ out,
+template <uint32_t Bins = kLutBins, int Passes = 1, uint32_t V = kPolyMax>
+__device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SamplePolyT<V>* __restrict__ out,
                                   uint32_t* __restrict__ lut = nullptr) {
-  __shared__ int32_t qx[kPolyMax], qy[kPolyMax];
+  static_assert(V <= 32 * kBlock, "items per thread fit a 32-bit mask");
+  __shared__ int32_t qx[V], qy[V];
   __shared__ uint32_t s_ok, s_m, s_desc, s_rot;
   __shared__ int32_t s_cx, s_cy;
   const uint32_t E = (m0 + kBlock - 1) / kBlock;
@@ -321,7 +323,7 @@ __device__ inline void build_poly(int32_t* px, int32_t* py, uint32_t m0, SampleP
     return;
   }
   // 4. wedge table: rotate to the smallest pseudo-angle, then bin.
-  __shared__ double s_t[kPolyMax];
+  __shared__ double s_t[V];
   const double ccx = s_cx, ccy = s_cy;
   if (ok) {
     for (uint32_t j = threadIdx.x; j < m; j += kBlock)
@@ -434,10 +436,9 @@ __device__ __forceinline__ void dir_minmax(const int2* __restrict__ sp, uint32_t
 }
 
 // Single set, before the fused pass. k_sample_dirs: workgroup b takes sample
-// points b*kSamplePer .. +kSamplePer-1 of kSampleN, taken as runs of
-// kSampleRun consecutive points spread evenly over [0, n) (run r starts at
-// floor(r n / (kSampleN / kSampleRun)); positions past the end clamp to the
-// last point) and writes, per direction, its largest dot
+// points b*kSamplePer .. +kSamplePer-1 of kSampleN spread evenly over [0, n)
+// (point floor(k n / kSampleN); single points, not the batch sampler's runs:
+// with runs the fused pass measured slower on normal data) and writes, per direction, its largest dot
 // product with that point's coordinates (one partial per workgroup and
 // direction, written contiguously, no atomics). k_sample_reduce: each
 // workgroup folds the partials of kReduceDirsPerBlock directions into the

@@ -221,9 +221,10 @@ def test_many_survivors_go_straight_to_large_path(ctx):
 @pytest.mark.parametrize("case", ["uniform", "ring", "polygon", "parabola"])
 def test_tile_round_path(case, wait):
     """The hull path through the tile rounds (CH_LARGE_DIRECT above the
-    survivor count: tile hulls, then a block hull, or the large-hull path
-    when a round stops shrinking), with either wait for the block hull's
-    result (watching its status word or the stream), against the oracle."""
+    survivor count, and no second polygon: tile hulls, then a block hull, or
+    the large-hull path when a round stops shrinking), with either wait for
+    the block hull's result (watching its status word or the stream),
+    against the oracle."""
     import os
     import paper_2209_12310_amd as ch
     _say(f"tile round path: {case}, wait {wait}")
@@ -236,9 +237,10 @@ def test_tile_round_path(case, wait):
     else:
         i = np.arange(20_000, dtype=np.int64)
         xy = to_xy(np.stack([48 * i, (i * i) >> 9], 1))
-    old = {k: os.environ.get(k) for k in ("CH_LARGE_DIRECT", "CH_HULL_WAIT")}
+    old = {k: os.environ.get(k) for k in ("CH_LARGE_DIRECT", "CH_HULL_WAIT", "CH_SECOND_POLY")}
     os.environ["CH_LARGE_DIRECT"] = str(1 << 30)
     os.environ["CH_HULL_WAIT"] = wait
+    os.environ["CH_SECOND_POLY"] = "0"
     try:
         c = ch.Context(0)
     finally:
@@ -250,10 +252,61 @@ def test_tile_round_path(case, wait):
     try:
         _check_hull(c, xy)
         info = c.last_hull_info()
+        assert info["refined"] == 0, info
         if info["survivors"] > 4096:
             assert info["rounds"] >= 1, info
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("case", ["uniform", "ring", "wide_ring", "wide_ring_dense", "square_sides",
+                                  "polygon", "dup_ring"])
+def test_second_polygon(ctx, case):
+    """Inputs whose survivors are too many for one workgroup: the second
+    polygon from the survivors drops those strictly inside it, then the block
+    hull, the rounds or the large-hull path finish; the hull equals the
+    oracle's. A lattice square's whole boundary, many points in convex
+    position, and every point twice are included."""
+    _say(f"second polygon: {case}")
+    if case == "uniform":
+        xy = workloads.uniform(30_000_000, 51)
+    elif case == "ring":
+        xy = workloads.annulus(2_000_000, 52)
+    elif case == "wide_ring":
+        xy = workloads.annulus(1_000_000, 53, 0.3, 0.5)
+    elif case == "wide_ring_dense":
+        xy = workloads.annulus(8_000_000, 57, 0.49, 0.5)
+    elif case == "square_sides":
+        rng = np.random.default_rng(54)
+        side = 30000
+        t = np.arange(side)
+        lo = 5000
+        edge = np.concatenate([
+            np.stack([lo + t, np.full(side, lo)], 1), np.stack([np.full(side, lo + side), lo + t], 1),
+            np.stack([lo + side - t, np.full(side, lo + side)], 1), np.stack([np.full(side, lo), lo + side - t], 1)])
+        inner = rng.integers(lo + 1, lo + side, (400_000, 2))
+        pts = np.concatenate([edge, inner])
+        xy = to_xy(pts[rng.permutation(len(pts))])
+    elif case == "polygon":
+        rng = np.random.default_rng(55)
+        poly = np.asarray(convex_lattice_polygon(60), np.int64) + 3000
+        c = (poly.min(0) + poly.max(0)) // 2
+        inner = rng.integers(-3000, 3000, (300_000, 2)) + c
+        pts = np.concatenate([poly, inner])
+        xy = to_xy(pts[rng.permutation(len(pts))])
+    else:
+        ring = workloads.annulus(500_000, 56, 0.4999, 0.5)
+        xy = np.concatenate([ring[::-1], ring])
+    _check_hull(ctx, xy)
+    info = ctx.last_hull_info()
+    # The second polygon runs exactly when one workgroup (4096 records)
+    # cannot take the survivors and there are at most 2^18 of them; these
+    # two always are in that range (the square's side points already fall to
+    # the octagon test, the rings keep more).
+    assert (info["refined"] > 0) == (4096 < info["survivors"] <= 1 << 18), info
+    assert info["refined"] <= info["survivors"], info
+    if case in ("polygon", "wide_ring_dense"):
+        assert info["refined"] > 0, info
 
 
 def test_max_points(ctx):

@@ -120,8 +120,7 @@ def test_domain_error_at_sampled_points(ctx, where):
     import paper_2209_12310_amd as ch
     n = SAMPLE_MIN + 999
     xy = workloads.annulus(n, 87, 0.49, 0.5)
-    # "sampled": point 3 of sample run 5 (runs of 16 start at floor(r n / 4096))
-    i = {"sampled": (5 * n) // 4096 + 3, "last": n - 1}.get(where, where)
+    i = {"sampled": (5 * n) // 16384, "last": n - 1}.get(where, where)
     xy[i, 1] = np.float32(np.nan)
     with pytest.raises(ch.DomainError):
         ctx.hull(_dev(xy))
