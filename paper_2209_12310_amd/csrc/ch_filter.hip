@@ -1566,10 +1566,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
                                                        const SetTile* __restrict__ tiles,
                                                        SetState* __restrict__ sets,
                                                        const SamplePoly* __restrict__ polys,
-                                                       const uint32_t* __restrict__ luts,
                                                        Rec* __restrict__ cand) {
   __shared__ int32_t s_pvx[kBatchDirs], s_pvy[kBatchDirs];
-  __shared__ uint32_t s_lut[kBatchLutBins];
   __shared__ float s_qx[kWaves][kQueue], s_qy[kWaves][kQueue];
   __shared__ uint32_t s_qg[kWaves][kQueue];
   __shared__ Rec s_cb[kWaves][kCapB];  // staged candidate records of the wave
@@ -1584,16 +1582,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
     const uint32_t pnv = min(sp->nv, (uint32_t)kBatchDirs);
     const bool use_sp = pnv >= 3;
     float pcx = 0.f, pcy = 0.f, pr2 = 0.f, pos = 0.f, pot = 0.f;
-    int32_t pcxi = 0, pcyi = 0;
-    __syncthreads();  // the previous tile is done with s_pvx / s_pvy / s_lut
+    __syncthreads();  // the previous tile is done with s_pvx / s_pvy
     if (use_sp) {
       for (uint32_t i = threadIdx.x; i < pnv; i += kBlock) { s_pvx[i] = sp->vx[i]; s_pvy[i] = sp->vy[i]; }
-      const uint32_t* __restrict__ lut = luts + size_t(st.set) * kBatchLutBins;
-      for (uint32_t i = threadIdx.x; i < kBatchLutBins; i += kBlock) s_lut[i] = lut[i];
-      pcxi = sp->cx;
-      pcyi = sp->cy;
-      pcx = (float)pcxi * (1.0f / kGridF);
-      pcy = (float)pcyi * (1.0f / kGridF);
+      pcx = (float)sp->cx * (1.0f / kGridF);
+      pcy = (float)sp->cy * (1.0f / kGridF);
       pr2 = sp->r2;
       pos = sp->os;
       pot = sp->ot;
@@ -1637,8 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
       }
       wave_sync();
       const bool keep = lane < (int)cnt &&
-                        !poly_lut_inside<kBatchLutBins>(s_pvx, s_pvy, pnv, s_lut, pcxi, pcyi,
-                                                        (int32_t)(x * kGridF), (int32_t)(y * kGridF));
+                        !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF));
       emit(keep, x, y, gl);
     };
     auto push = [&](bool qq, float x, float y, uint32_t gl) {
@@ -1720,8 +1712,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
         const uint32_t g = singles[i];
         const float x = xy[2 * (size_t)g], y = xy[2 * (size_t)g + 1];
         keys_add(k, x, y, bad);
-        if (!use_sp || !poly_lut_inside<kBatchLutBins>(s_pvx, s_pvy, pnv, s_lut, pcxi, pcyi,
-                                                       (int32_t)(x * kGridF), (int32_t)(y * kGridF)))
+        if (!use_sp ||
+            !poly_strict_inside(s_pvx, s_pvy, pnv, (int32_t)(x * kGridF), (int32_t)(y * kGridF)))
           cand[base + atomicAdd(&ss.ncand, 1u)] = make_payload<Rec>(g - base, x, y);
       }
     }
@@ -1739,13 +1731,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
   }
 }
 
-// Candidates per set from which the batch candidates get a second polygon.
+// Candidates per set from which the batch candidates get a second polygon,
+// and its bins.
 constexpr uint32_t kRefineMin = 1024;
+constexpr uint32_t kRefineBatchBins = 512;
 
 // Whole workgroup, one set's m >= kRefineMin candidates (every point not
 // strictly inside its sample polygon, or all its points) and a point c
 // inside its hull: a second polygon from the candidates themselves. The plane around c is cut
-// into kBatchDirs bins of pseudo-angle; in each bin the candidate of largest
+// into kRefineBatchBins bins of pseudo-angle; in each bin the candidate of largest
 // dot product with the bin's middle direction is kept (a 64-bit LDS max of
 // (dot product, position)), and the kept points, in bin order, go through
 // build_poly (repeats and reflex points dropped until none is left, then the
@@ -1758,15 +1752,15 @@ constexpr uint32_t kRefineMin = 1024;
 // as close to the hull as its number of sides allows.
 __device__ void refine_poly(const Rec* __restrict__ cand, uint32_t m, int32_t cx, int32_t cy,
                             SamplePoly* __restrict__ out, uint32_t* __restrict__ lut) {
-  static_assert(kBatchDirs == (uint32_t)kBlock, "one bin per thread");
-  __shared__ uint64_t s_bin[kBatchDirs];
-  __shared__ int32_t s_da[kBatchDirs], s_db[kBatchDirs];
-  __shared__ int32_t s_px[kBatchDirs], s_py[kBatchDirs];
-  {
-    // Bin k: pseudo-angles [4k, 4k + 4) / kBatchDirs; its middle direction as
-    // an integer vector with |a| + |b| = 1024 (dot products below 2^30).
-    const uint32_t k = threadIdx.x;
-    const float pa = ((float)k + 0.5f) * (4.0f / (float)kBatchDirs);
+  constexpr uint32_t B = kRefineBatchBins, E = B / kBlock;
+  static_assert(B % kBlock == 0 && B <= kPolyMax, "whole bins per thread, within the polygon");
+  __shared__ uint64_t s_bin[B];
+  __shared__ int32_t s_da[B], s_db[B];
+  __shared__ int32_t s_px[B], s_py[B];
+  for (uint32_t k = threadIdx.x; k < B; k += kBlock) {
+    // Bin k: pseudo-angles [4k, 4k + 4) / B; its middle direction as an
+    // integer vector with |a| + |b| = 1024 (dot products below 2^30).
+    const float pa = ((float)k + 0.5f) * (4.0f / (float)B);
     const uint32_t q = (uint32_t)pa;
     const int32_t f = (int32_t)__builtin_rintf((pa - (float)q) * 1024.0f);
     const int32_t u = 1024 - f, v = f;
@@ -1788,19 +1782,30 @@ __device__ void refine_poly(const Rec* __restrict__ cand, uint32_t m, int32_t cx
       const uint32_t i = i0 + j * kBlock;
       const float dx = (float)(r[j].x - cx), dy = (float)(r[j].y - cy);
       if (i >= m || (dx == 0.f && dy == 0.f)) continue;
-      const uint32_t k = min((uint32_t)(pangle32(dx, dy) * (float)(kBatchDirs / 4)), kBatchDirs - 1);
+      const uint32_t k = min((uint32_t)(pangle32(dx, dy) * (float)(B / 4)), B - 1);
       const int32_t dot = __mul24(s_da[k], r[j].x) + __mul24(s_db[k], r[j].y) + (1 << 30);
       atomicMax(&s_bin[k], ((uint64_t)(uint32_t)dot << 32) | i);
     }
   }
   __syncthreads();
-  const uint64_t key = s_bin[threadIdx.x];
+  // Thread t takes bins tE .. tE + E - 1 (bin order kept by the scan).
+  uint64_t key[E];
+  uint32_t nk = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    key[e] = s_bin[threadIdx.x * E + e];
+    nk += key[e] ? 1u : 0u;
+  }
   uint32_t mp;
-  const uint32_t pos = block_excl_scan(key ? 1u : 0u, mp);
-  if (key) {
-    const Rec r = cand[(uint32_t)key];
-    s_px[pos] = r.x;
-    s_py[pos] = r.y;
+  uint32_t pos = block_excl_scan(nk, mp);
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) {
+    if (key[e]) {
+      const Rec r = cand[(uint32_t)key[e]];
+      s_px[pos] = r.x;
+      s_py[pos] = r.y;
+      ++pos;
+    }
   }
   __syncthreads();
   build_poly<kBatchLutBins, 16>(s_px, s_py, mp, out, lut);
@@ -1895,7 +1900,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restric
                                                        Rec* __restrict__ surv,
                                                        const SamplePoly* __restrict__ polys,
                                                        const uint32_t* __restrict__ luts) {
-  __shared__ int32_t s_pvx[kBatchDirs], s_pvy[kBatchDirs];
+  __shared__ int32_t s_pvx[kPolyMax], s_pvy[kPolyMax];
   __shared__ uint32_t s_lut[kBatchLutBins];
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -1907,7 +1912,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restric
     const Octagon* __restrict__ o = &ss.oct;
     const uint32_t base = (uint32_t)off[s];
     // Second polygon (block-uniform decision).
-    const uint32_t nv2 = ss.ncand >= kRefineMin ? min(polys[s].nv, (uint32_t)kBatchDirs) : 0u;
+    const uint32_t nv2 = ss.ncand >= kRefineMin ? min(polys[s].nv, (uint32_t)kPolyMax) : 0u;
     const int32_t cx2 = polys[s].cx, cy2 = polys[s].cy;
     __syncthreads();  // the previous tile is done with s_pvx / s_pvy / s_lut
     if (nv2 >= 3) {
@@ -2053,8 +2058,8 @@ hipError_t launch_oct_out(const Header* hdr, void* d_oct, hipStream_t st) {
 namespace chk {
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, BatchHdr* bh,
-                               const uint32_t* slist, SamplePoly* polys, uint32_t* luts,
-                               uint32_t sample_min, uint32_t grid, hipStream_t st);
+                               const uint32_t* slist, SamplePoly* polys, uint32_t sample_min,
+                               uint32_t grid, hipStream_t st);
 
 hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32_t nsets,
                                     uint64_t total_points, uint32_t tile, BatchHdr* bh,
@@ -2068,11 +2073,11 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
   });
   hipError_t e = hipSuccess;
   hooked(hk, "batch_sample",
-         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, luts, sample_min, sample_grid, st); });
+         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, sample_min, sample_grid, st); });
   if (e != hipSuccess) return e;
   hooked(hk, "batch_pass", [&] {
     hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
-                       luts, cand);
+                       cand);
   });
   hooked(hk, "batch_octagon", [&] {
     hipLaunchKernelGGL(k_batch_octagon, dim3((nsets + kWaves - 1) / kWaves), dim3(kBlock), 0, st, off,

@@ -73,9 +73,10 @@ __device__ inline uint32_t octagon_sieve(const int2 (&v)[P], int2* sp, int64_t (
 // sample_min (and kBatchSample) points; the workgroups take the sets of the
 // plan's list (longest jobs first) one at a time through a shared counter.
 // Per set: batch_chunks chunks of kBatchSample sample points, kBatchDirs
-// directions, the polygon in the set's SamplePoly with its wedge table of
-// kBatchLutBins bins in luts (the plan clears the polygon of the other
-// sets). The direction
+// directions, the polygon in the set's SamplePoly (the plan clears the
+// polygon of the other sets; the pass tests against it by a binary search,
+// no wedge table: building one per set cost the sampler more than it saved
+// the pass). The direction
 // scans run over a chunk's points left by octagon_sieve. A chunk's points
 // are runs of kSampleRun consecutive input points (one 128-byte line each)
 // with the runs spread evenly over the set: a sample point per line fetched,
@@ -85,7 +86,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
                                                          BatchHdr* __restrict__ bh,
                                                          const uint32_t* __restrict__ slist,
                                                          SamplePoly* __restrict__ polys,
-                                                         uint32_t* __restrict__ luts,
                                                          uint32_t sample_min) {
   // Thread t takes direction pair t % kPairs (a direction and its opposite)
   // over half t / kPairs of each chunk's sample; the halves are combined.
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict
       py[pr + kPairs] = pmin.y;
     }
     __syncthreads();
-    build_poly<kBatchLutBins>(px, py, kBatchDirs, &polys[s], luts + size_t(s) * kBatchLutBins);
+    build_poly(px, py, kBatchDirs, &polys[s]);
   }
 }
 
@@ -438,10 +438,10 @@ hipError_t launch_sample_poly(const float* xy, uint32_t n, void* scratch, Sample
 }
 
 hipError_t launch_batch_sample(const float* xy, const uint64_t* off, BatchHdr* bh,
-                               const uint32_t* slist, SamplePoly* polys, uint32_t* luts,
-                               uint32_t sample_min, uint32_t grid, hipStream_t st) {
+                               const uint32_t* slist, SamplePoly* polys, uint32_t sample_min,
+                               uint32_t grid, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_sample, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, slist, polys,
-                     luts, sample_min);
+                     sample_min);
   return hipGetLastError();
 }
 
