@@ -1534,20 +1534,86 @@ __device__ uint32_t big_set_hull(BigSmem& sm, Rec* X, Rec* Y, uint32_t c, int32_
 
 // ------------------------------------------------------------- batch mode
 
+// The first block-hull list: every set, those with the most survivors of
+// the candidates' test first (buckets of more than 1024, 257-1024, 65-256
+// and at most 64, each in set order), so that the longest block hulls start
+// first. Workgroup b ranks sets b kBlock .. b kBlock + kBlock - 1 after
+// counting every set's bucket (a strided pass over the set states, from L2).
+__global__ __launch_bounds__(kBlock) void k_batch_final_plan(uint32_t nsets,
+                                                             BatchHdr* __restrict__ bh,
+                                                             const SetState* __restrict__ sets,
+                                                             uint32_t* __restrict__ order) {
+  constexpr int kVals = 8;  // 4 buckets before this workgroup's sets, 4 in all
+  __shared__ uint32_t s_red[kWaves][kVals];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t first = blockIdx.x * kBlock;
+  auto bucket = [&](uint32_t s) {
+    const uint32_t c = sets[s].cnt[0];
+    return c > 1024 ? 0u : (c > 256 ? 1u : (c > 64 ? 2u : 3u));
+  };
+  uint32_t v[kVals] = {};
+  for (uint32_t s = threadIdx.x; s < nsets; s += kBlock) {
+    const uint32_t b = bucket(s);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint32_t hit = b == k ? 1u : 0u;
+      v[4 + k] += hit;
+      v[k] += s < first ? hit : 0u;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kVals; ++k) {
+    const uint32_t r = wave_allreduce(v[k], [](uint32_t a, uint32_t b) { return a + b; });
+    if (lane == 0) s_red[w][k] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kVals; ++k) {
+    v[k] = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v[k] += s_red[q][k];
+  }
+  const uint32_t s = first + threadIdx.x;
+  const bool own = s < nsets;
+  const uint32_t b = own ? bucket(s) : 4u;
+  uint32_t unused;
+  const uint32_t e01 = block_excl_scan(own && b < 2 ? 1u << (16 * b) : 0u, unused);
+  const uint32_t e23 = block_excl_scan(own && b >= 2 && b < 4 ? 1u << (16 * (b - 2)) : 0u, unused);
+  if (own) {
+    const uint32_t rank = ((b < 2 ? e01 : e23) >> (16 * (b & 1))) & 0xFFFFu;
+    uint32_t start = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) start += j < b ? v[4 + j] : (j == b ? v[j] : 0u);
+    order[start + rank] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) bh->final_next = 0;
+}
+
 // Hull of every set whose candidates fit one block (<= T); a set still above
 // that waits for the next tile-hull round (or, after the last one, for
-// k_batch_large). Workgroups take sets with a fixed stride.
+// k_batch_large). With `order` the workgroups take the sets of that list
+// through a shared counter (the first stage), else with a fixed stride.
 template <int T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_final(const uint64_t* __restrict__ off,
                                                         uint32_t nsets,
-                                                        const BatchHdr* __restrict__ bh,
+                                                        BatchHdr* __restrict__ bh,
                                                         SetState* __restrict__ sets, int stage,
                                                         const Rec* __restrict__ recs,
                                                         uint32_t* __restrict__ hull_idx,
-                                                        uint32_t* __restrict__ hull_count) {
+                                                        uint32_t* __restrict__ hull_count,
+                                                        const uint32_t* __restrict__ order) {
   __shared__ HullSmem<T> sm;
+  __shared__ uint32_t s_item;
   const bool bad_off = bh->bad_offsets != 0;
-  for (uint32_t s = blockIdx.x; s < nsets; s += gridDim.x) {
+  for (uint32_t it = blockIdx.x;; it += gridDim.x) {
+    uint32_t s = it;
+    if (order) {
+      __syncthreads();  // every thread has read s_item
+      if (threadIdx.x == 0) s_item = atomicAdd(&bh->final_next, 1u);
+      __syncthreads();
+      s = s_item < nsets ? order[s_item] : nsets;
+    }
+    if (s >= nsets) break;
     SetState& ss = sets[s];
     if (ss.done) continue;
     if (bad_off) {
@@ -1737,11 +1803,15 @@ namespace chk {
 hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
                                   SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
-                                  hipStream_t st, LaunchHook* hk) {
+                                  uint32_t* order, hipStream_t st, LaunchHook* hk) {
   Rec* buf[2] = {recA, recB};
+  hooked(hk, "batch_final_plan", [&] {
+    hipLaunchKernelGGL(k_batch_final_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, nsets, bh,
+                       sets, order);
+  });
   hooked(hk, "batch_final", [&] {
     hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                       sets, 0, recA, hull_idx, hull_count);
+                       sets, 0, recA, hull_idx, hull_count, order);
   });
   for (int r = 0; r < kBatchRounds; ++r) {
     hooked(hk, "batch_round_plan", [&] {
@@ -1755,10 +1825,10 @@ hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr*
     hooked(hk, "batch_final", [&] {
       if (r + 1 < kBatchRounds)
         hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
+                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, nullptr);
       else
         hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
-                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count);
+                           sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, nullptr);
     });
   }
   // Sets whose candidates did not shrink to one workgroup: the last round
