@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2209_12310_amd import workloads
-from tests._shapes import lattice_circle, to_xy
+from tests._shapes import convex_lattice_polygon, lattice_circle, to_xy
 
 pytestmark = pytest.mark.gpu
 
@@ -78,6 +78,41 @@ def test_degenerate_sets(ctx):
         np.zeros((0, 2), np.float32),
         to_xy([(1, 2), (3, 4)]),
     ]
+    _check_sets(ctx, sets)
+
+
+def test_second_polygon_sets(ctx):
+    """Sets with at least 1024 candidates, so each gets a second polygon
+    built from its candidates: points on a line, one point repeated, two
+    points repeated, a square's whole lattice boundary with interior points
+    (points on the polygon's sides), a convex lattice polygon (every point a
+    hull vertex), thin and wide rings, a lattice circle with interior
+    points, and sets with and without a sample polygon."""
+    _say("batch second polygon sets")
+    rng = np.random.default_rng(61)
+    line = np.array([(x, 2 * x + 5) for x in range(0, 40000, 7)], np.int64)
+    side = 3000
+    t = np.arange(side)
+    edge = np.concatenate([np.stack([10 + t, np.full(side, 10)], 1), np.stack([np.full(side, 10 + side), 10 + t], 1),
+                           np.stack([10 + side - t, np.full(side, 10 + side)], 1),
+                           np.stack([np.full(side, 10), 10 + side - t], 1)])
+    square = np.concatenate([edge, rng.integers(11, 10 + side, (20000, 2))])
+    poly = np.asarray(convex_lattice_polygon(25), np.int64) + 100
+    circ = np.asarray(lattice_circle(5 * 13 * 17 * 29), np.int64)  # centred at 2^19
+    circ_in = np.concatenate([circ, rng.integers(-20000, 20000, (30000, 2)) + (1 << 19)])
+    shuf = lambda a: to_xy(a[rng.permutation(len(a))])
+    sets = [
+        shuf(line),
+        to_xy([(77, 99)] * 3000),
+        to_xy([(5, 6)] * 1500 + [(900, 4)] * 1500),
+        shuf(square),
+        shuf(poly),
+        workloads.annulus(60_000, 62, 0.4999, 0.5),
+        workloads.annulus(9_000, 63, 0.3, 0.5),
+        shuf(circ_in),
+        workloads.by_kind("uniform", 5000, 64),
+    ]
+    assert len(poly) > 1024 and len(circ) > 16
     _check_sets(ctx, sets)
 
 
