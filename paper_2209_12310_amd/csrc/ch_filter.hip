@@ -1532,6 +1532,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(const uint64_t* __restric
     bh->nsampled = v[6] + v[7] + v[8] + v[9];
     bh->sample_next = 0;
     bh->refine_next = 0;
+    bh->pass_next = 0;
   }
 }
 
@@ -1562,7 +1563,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_octagon(const uint64_t* __rest
 // with 64-bit atomic max on an order-preserving encoding.
 __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__ xy,
                                                        const uint64_t* __restrict__ off,
-                                                       const BatchHdr* __restrict__ bh,
+                                                       BatchHdr* __restrict__ bh,
                                                        const SetTile* __restrict__ tiles,
                                                        SetState* __restrict__ sets,
                                                        const SamplePoly* __restrict__ polys,
@@ -1574,7 +1575,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(const float* __restrict__
   const uint32_t ntiles = bh->ntiles;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  __shared__ uint32_t s_t;
+  for (;;) {
+    // Tiles through a shared counter: a workgroup that drew short tiles
+    // takes more instead of waiting on a fixed share.
+    __syncthreads();  // every thread has read s_t
+    if (threadIdx.x == 0) s_t = atomicAdd(&bh->pass_next, 1u);
+    __syncthreads();
+    const uint32_t t = s_t;
+    if (t >= ntiles) break;
     const SetTile st = tiles[t];
     SetState& ss = sets[st.set];
     // The set's sample polygon, if it has one (block-uniform).
@@ -2092,8 +2101,10 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                        bh, sets, tiles);
   });
   hooked(hk, "batch_cand", [&] {
-    hipLaunchKernelGGL(k_batch_cand, dim3(grid), dim3(kBlock), 0, st, off, bh, sets, tiles, cand, recs,
-                       polys, luts);
+    // its own grid (16 workgroups per CU): the candidate tiles are short
+    // latency chains, which more workgroups than the pass's overlap better
+    hipLaunchKernelGGL(k_batch_cand, dim3(4 * sample_grid), dim3(kBlock), 0, st, off, bh, sets, tiles,
+                       cand, recs, polys, luts);
   });
   return hipGetLastError();
 }

@@ -287,7 +287,8 @@ struct BatchHdr {
   uint32_t refine_next;              // next set a second-polygon workgroup takes
   uint32_t ncand_tiles;              // tiles of the candidates' octagon test
   uint32_t final_next;               // next entry of the first block-hull list
-  uint32_t pad[5];
+  uint32_t pass_next;                // next pass tile a workgroup takes
+  uint32_t pad[4];
 };
 
 // Per-set state, one struct per set.
