@@ -125,7 +125,7 @@ struct Rec {           // a candidate hull point: grid coordinates + index
 // inner grid point, then exactly.
 constexpr int kPolyMax = 512;              // directions (and at most vertices), single set
 constexpr uint32_t kLutBins = 2048;        // single set: pseudo-angle bins of the wedge table
-constexpr uint32_t kBatchLutBins = 1024;   // batch: wedge-table bins per set
+constexpr uint32_t kBatchLutBins = 1024;   // batch: wedge-table bins of a set's second polygon
 constexpr uint32_t kSampleN = 65536;       // single set: sample points
 constexpr uint32_t kSamplePer = 256;       // sample points per direction workgroup
 constexpr uint32_t kSampleRun = 16;        // batch: consecutive points per sample run (128 bytes)

@@ -68,8 +68,9 @@ __device__ __forceinline__ float pangle32(float dx, float dy) {
 // Wedge table of a polygon about its centre c: the vertices, in
 // counter-clockwise order starting at the smallest pseudo-angle, split the
 // plane around c into wedges (wedge j between vertices j and j+1, the last
-// one wrapping through angle 0). Bin k of Bins (kLutBins for one set,
-// kBatchLutBins per batch set) covers the pseudo-angles
+// one wrapping through angle 0). Bin k of Bins (kLutBins for the sample
+// polygon of one set, kRefineLut and kBatchLutBins for the second polygons)
+// covers the pseudo-angles
 // [k w - eps, (k+1) w + eps], w = 4 / Bins, eps = 2^-16 (far above the
 // error of pangle32); its entry holds the first wedge meeting that interval
 // (low 16 bits) and the number of consecutive wedges that do (high 16 bits).
