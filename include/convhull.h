@@ -80,7 +80,13 @@ typedef struct {
 /* Create a context bound to HIP device `hip_device`. tune_cache_path (may be
  * NULL) names a text file of batch tuning results (see ch_tune_batch); it is
  * read here if it exists. Allocates pinned host staging memory and nothing
- * on the device.
+ * on the device. Environment variables read here (tests and measurement;
+ * none changes a result): CH_REDUCE_BLOCKS, CH_FILTER_BLOCKS,
+ * CH_FUSED_BLOCKS, CH_NARROW_BLOCKS (grid sizes of the streaming passes),
+ * CH_HULL_WAIT=stream (wait for ch_hull's stream instead of watching the
+ * result block), CH_LARGE_DIRECT (survivors from which ch_hull goes
+ * straight to the large-hull path), CH_SECOND_POLY=0 (no second polygon in
+ * ch_hull).
  * Errors: CH_E_INVALID_ARG (out is NULL), CH_E_DEVICE, CH_E_NOMEM. */
 ch_status ch_ctx_create(int hip_device, const char* tune_cache_path, ch_ctx** out);
 /* Destroy a context (NULL is ignored). Waits for nothing: the caller must
