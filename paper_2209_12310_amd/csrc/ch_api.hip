@@ -668,7 +668,7 @@ ch_status ch_hull(ch_ctx* ctx, const float* d_xy, uint32_t n, uint32_t* h_hull_i
   uint32_t* res_idx = at<uint32_t>(d_ws, L.res_idx);
   Rec* srec = at<Rec>(d_ws, L.surv);
   Rec* rec[2] = {at<Rec>(d_ws, L.recA), at<Rec>(d_ws, L.recB)};
-  // Candidates of the fused pass go to list B (first written again by round 1).
+  // Candidates of the fused pass go to list B (first written again by the second tile-hull round).
   if (ch_status s = run_filter(ctx, d_xy, n, nullptr, &hdr->count, nullptr, d_ws, L, st, srec,
                                rec[1]))
     return s;
