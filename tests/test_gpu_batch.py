@@ -58,6 +58,21 @@ def test_mixed_small_sets(ctx):
     _check_sets(ctx, sets)
 
 
+@pytest.mark.parametrize("nsets", [1, 255, 256, 257, 513])
+def test_set_counts_at_workgroup_boundaries(ctx, nsets):
+    """Set counts around multiples of 256 (the plan kernels give each
+    workgroup 256 sets and rank them against all the others), with sets
+    large enough to get sample polygons and second polygons mixed with
+    small and empty ones."""
+    _say(f"batch set count {nsets}")
+    rng = np.random.default_rng(70 + nsets)
+    sets = []
+    for i in range(nsets):
+        n = int(rng.choice([0, 5, 900, 3000, 9000, 40000]))
+        sets.append(workloads.by_kind(("uniform", "normal", "annulus_wide")[i % 3], n, 1000 + i))
+    _check_sets(ctx, sets)
+
+
 def test_batch_equals_solo(ctx):
     _say("batch equals solo")
     import torch
