@@ -63,8 +63,8 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
                                     uint32_t sample_grid, uint32_t* slist, uint32_t* luts,
                                     hipStream_t st, LaunchHook* hk);
-hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
-                                  SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
+hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, uint64_t total_points,
+                                  BatchHdr* bh, SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
                                   uint32_t* order, hipStream_t st, LaunchHook* hk);
 hipError_t launch_axis_extremes(const float* xy, uint32_t n, uint32_t head, double* partials,
@@ -470,7 +470,7 @@ ch_status run_batch(ch_ctx* ctx, const ch_batch_params& p, const float* d_xy,
                                           (uint32_t)ctx->cu_count * 4, at<uint32_t>(d_ws, L.slist),
                                           at<uint32_t>(d_ws, L.luts), st, hk);
   if (e != hipSuccess) return hip_fail(ctx, e, "batch filter launch");
-  e = launch_batch_hull_side(d_off, nsets, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
+  e = launch_batch_hull_side(d_off, nsets, total_points, bh, sets, at<SetTile>(d_ws, L.rtiles), recA, recB,
                              d_hull_idx, d_hull_count, p.hull_blocks, at<uint32_t>(d_ws, L.slist), st,
                              hk);
   if (e != hipSuccess) return hip_fail(ctx, e, "batch hull launch");

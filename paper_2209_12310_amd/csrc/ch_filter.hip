@@ -2076,16 +2076,22 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                                     Rec* cand, uint32_t grid, uint32_t sample_min,
                                     uint32_t sample_grid, uint32_t* slist, uint32_t* luts,
                                     hipStream_t st, LaunchHook* hk) {
+  // Grids above the most workgroups with work (sets, or tiles: at most one
+  // partial tile per set) only add dispatch time, which small batches feel.
+  auto cap = [](uint64_t g, uint64_t most) { return (uint32_t)(most < 1 ? 1 : (g < most ? g : most)); };
+  const uint32_t g_sets = cap(sample_grid, nsets);
+  const uint32_t g_pass = cap(grid, total_points / tile + nsets);
+  const uint32_t g_cand = cap(4ull * sample_grid, total_points / kCandTile + nsets);
   hooked(hk, "batch_plan", [&] {
     hipLaunchKernelGGL(k_batch_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, off, nsets,
                        total_points, tile, sample_min, bh, sets, tiles, polys, slist);
   });
   hipError_t e = hipSuccess;
   hooked(hk, "batch_sample",
-         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, sample_min, sample_grid, st); });
+         [&] { e = launch_batch_sample(xy, off, bh, slist, polys, sample_min, g_sets, st); });
   if (e != hipSuccess) return e;
   hooked(hk, "batch_pass", [&] {
-    hipLaunchKernelGGL(k_batch_pass, dim3(grid), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
+    hipLaunchKernelGGL(k_batch_pass, dim3(g_pass), dim3(kBlock), 0, st, xy, off, bh, tiles, sets, polys,
                        cand);
   });
   hooked(hk, "batch_octagon", [&] {
@@ -2093,7 +2099,7 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
                        nsets, bh, sets);
   });
   hooked(hk, "batch_refine", [&] {
-    hipLaunchKernelGGL(k_batch_refine, dim3(sample_grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
+    hipLaunchKernelGGL(k_batch_refine, dim3(g_sets), dim3(kBlock), 0, st, off, nsets, bh, sets,
                        cand, polys, luts);
   });
   hooked(hk, "batch_cand_plan", [&] {
@@ -2103,7 +2109,7 @@ hipError_t launch_batch_filter_side(const float* xy, const uint64_t* off, uint32
   hooked(hk, "batch_cand", [&] {
     // its own grid (16 workgroups per CU): the candidate tiles are short
     // latency chains, which more workgroups than the pass's overlap better
-    hipLaunchKernelGGL(k_batch_cand, dim3(4 * sample_grid), dim3(kBlock), 0, st, off, bh, sets, tiles,
+    hipLaunchKernelGGL(k_batch_cand, dim3(g_cand), dim3(kBlock), 0, st, off, bh, sets, tiles,
                        cand, recs, polys, luts);
   });
   return hipGetLastError();

@@ -1800,17 +1800,22 @@ hipError_t launch_large_path(const Rec* in, const uint32_t* in_count, uint32_t m
 
 namespace chk {
 
-hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr* bh,
-                                  SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
+hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, uint64_t total_points,
+                                  BatchHdr* bh, SetState* sets, SetTile* rtiles, Rec* recA, Rec* recB,
                                   uint32_t* hull_idx, uint32_t* hull_count, uint32_t grid,
                                   uint32_t* order, hipStream_t st, LaunchHook* hk) {
   Rec* buf[2] = {recA, recB};
+  // Grids above the most workgroups with work (sets, or round tiles) only
+  // add dispatch time, which small batches feel.
+  auto cap = [](uint64_t g, uint64_t most) { return (uint32_t)(most < 1 ? 1 : (g < most ? g : most)); };
+  const uint32_t g_sets = cap(grid, nsets);
+  const uint32_t g_tiles = cap(grid, total_points / kHullTile + nsets);
   hooked(hk, "batch_final_plan", [&] {
     hipLaunchKernelGGL(k_batch_final_plan, dim3(nsets / kBlock + 1), dim3(kBlock), 0, st, nsets, bh,
                        sets, order);
   });
   hooked(hk, "batch_final", [&] {
-    hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+    hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(g_sets), dim3(kBlock), 0, st, off, nsets, bh,
                        sets, 0, recA, hull_idx, hull_count, order);
   });
   for (int r = 0; r < kBatchRounds; ++r) {
@@ -1819,22 +1824,22 @@ hipError_t launch_batch_hull_side(const uint64_t* off, uint32_t nsets, BatchHdr*
                          nsets, bh, sets, r, rtiles);
     });
     hooked(hk, "batch_round", [&] {
-      hipLaunchKernelGGL(k_batch_round, dim3(grid), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,
+      hipLaunchKernelGGL(k_batch_round, dim3(g_tiles), dim3(kBlock), 0, st, off, bh, r, rtiles, sets,
                          buf[r & 1], buf[(r + 1) & 1]);
     });
     hooked(hk, "batch_final", [&] {
       if (r + 1 < kBatchRounds)
-        hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+        hipLaunchKernelGGL(k_batch_final<kHullTile>, dim3(g_sets), dim3(kBlock), 0, st, off, nsets, bh,
                            sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, nullptr);
       else
-        hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh,
+        hipLaunchKernelGGL(k_batch_final<kFinalTile>, dim3(g_sets), dim3(kBlock), 0, st, off, nsets, bh,
                            sets, r + 1, buf[(r + 1) & 1], hull_idx, hull_count, nullptr);
     });
   }
   // Sets whose candidates did not shrink to one workgroup: the last round
   // wrote them to buf[kBatchRounds & 1].
   hooked(hk, "batch_large", [&] {
-    hipLaunchKernelGGL(k_batch_large, dim3(grid), dim3(kBlock), 0, st, off, nsets, bh, sets,
+    hipLaunchKernelGGL(k_batch_large, dim3(g_sets), dim3(kBlock), 0, st, off, nsets, bh, sets,
                        buf[kBatchRounds & 1], buf[(kBatchRounds + 1) & 1], hull_idx, hull_count);
   });
   return hipGetLastError();
