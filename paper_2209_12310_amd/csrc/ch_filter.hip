@@ -1900,8 +1900,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_cand_plan(const uint64_t* __re
 // The octagon test of the candidates, a tile of them per workgroup at a
 // time; survivors appended as records to the set's slice of `surv`, their
 // count in cnt[0]. In a set with a second polygon (at least kRefineMin
-// candidates) a candidate strictly inside it is dropped too.
-__global__ __launch_bounds__(kBlock) void k_batch_cand(const uint64_t* __restrict__ off,
+// candidates) a candidate strictly inside it is dropped too. Five waves per
+// SIMD (at most 96 VGPRs) rather than four: more tiles' record loads in flight.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_cand(const uint64_t* __restrict__ off,
                                                        const BatchHdr* __restrict__ bh,
                                                        SetState* __restrict__ sets,
                                                        const SetTile* __restrict__ ctiles,

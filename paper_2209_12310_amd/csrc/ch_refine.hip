@@ -80,8 +80,10 @@ __device__ inline uint32_t octagon_sieve(const int2 (&v)[P], int2* sp, int64_t (
 // scans run over a chunk's points left by octagon_sieve. A chunk's points
 // are runs of kSampleRun consecutive input points (one 128-byte line each)
 // with the runs spread evenly over the set: a sample point per line fetched,
-// where single points at a large stride would fetch a line each.
-__global__ __launch_bounds__(kBlock) void k_batch_sample(const float* __restrict__ xy,
+// where single points at a large stride would fetch a line each. Four
+// workgroups per CU (at most 128 VGPRs, a few spilled) keep more sets' sample
+// loads in flight than three.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_sample(const float* __restrict__ xy,
                                                          const uint64_t* __restrict__ off,
                                                          BatchHdr* __restrict__ bh,
                                                          const uint32_t* __restrict__ slist,
