@@ -1,6 +1,6 @@
 // CPU unit test of the request server's scheduler (ch_sched.hpp) with a fake
 // executor and a fake clock: admission under the slot budget, arrival
-// order, back-pressure, time-outs, capacity retries, per-ticket failure
+// order, the point and set caps, back-pressure, time-outs, capacity retries, per-ticket failure
 // statuses injected by the executor, shutdown, the latency percentiles, and
 // many submitting / waiting / working threads at once (built with a thread
 // sanitizer by tests/test_serve_scheduler.py). Prints "ok" and exits 0 when
@@ -100,6 +100,50 @@ void test_batching_budget_and_order() {
   uint64_t done = 0, nb = 0;
   s.stats(&done, &nb, nullptr, nullptr, nullptr);
   CHECK(done == t.size() && nb == (uint64_t)batches);
+}
+
+// The point cap (max_batch_points) and the set cap (max_batch_sets): a
+// batch of several requests stays within both, a request above the point
+// cap runs alone, and arrival order holds across batches.
+void test_batch_point_and_set_caps() {
+  chs::Config c = make_cfg(1u << 30);
+  c.max_batch_points = 500;
+  c.max_batch_sets = 3;
+  chs::Scheduler s(c);
+  std::vector<float> data(5000, 0.25f);
+  const uint32_t sizes[] = {100, 100, 100, 100, 900, 10, 10, 480, 30, 1, 1, 1, 1};
+  std::vector<uint64_t> t;
+  for (uint32_t n : sizes) {
+    uint64_t k = 0;
+    CHECK(s.submit(data.data(), n, &k) == CH_OK);
+    t.push_back(k);
+  }
+  std::vector<chs::Request*> b;
+  std::vector<uint32_t> order;
+  std::vector<size_t> lens;
+  size_t left = sizeof(sizes) / sizeof(sizes[0]);
+  while (left) {
+    CHECK(s.next_batch(b));
+    CHECK(!b.empty() && b.size() <= 3);
+    uint64_t pts = 0;
+    for (auto* r : b) { pts += r->n; order.push_back(r->n); }
+    if (b.size() > 1) CHECK(pts <= 500);
+    lens.push_back(b.size());
+    execute(b);
+    s.finish(b);
+    left -= b.size();
+  }
+  for (size_t i = 0; i < order.size(); ++i) CHECK(order[i] == sizes[i]);
+  // Greedy in arrival order: {100,100,100} (set cap), {100} (900 would pass
+  // the point cap), {900} alone, {10,10,480}, {30,1,1} (set cap), {1,1}.
+  const size_t want[] = {3, 1, 1, 3, 3, 2};
+  CHECK(lens.size() == sizeof(want) / sizeof(want[0]));
+  for (size_t i = 0; i < lens.size() && i < sizeof(want) / sizeof(want[0]); ++i) CHECK(lens[i] == want[i]);
+  for (size_t i = 0; i < t.size(); ++i) {
+    uint32_t hull[2], h = 0;
+    CHECK(s.wait(t[i], 0, hull, 2, &h, nullptr) == CH_OK);
+    CHECK(h == 2 && hull[0] == sizes[i]);
+  }
 }
 
 void test_admission_errors_and_backpressure() {
@@ -318,6 +362,7 @@ void test_histogram() {
 int main() {
   test_histogram();
   test_batching_budget_and_order();
+  test_batch_point_and_set_caps();
   test_admission_errors_and_backpressure();
   test_injected_failures_per_ticket();
   test_percentiles_with_a_fake_clock();
